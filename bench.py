@@ -1,0 +1,339 @@
+#!/usr/bin/env python3
+"""Frame-rate bench of the per-frame rendering path on one MI355X.
+
+Workload (synthetic, seeded): 20M points from 4 simulated scans of a 40 x 30 x 6 m
+multi-room scene (1 m grid cells), a 120-frame orbit camera path at 1920x1080
+(90 degree horizontal fov), depth filter with 5 levels and filter_strength 0.5,
+U-Net with widths 32/64/128/256 and He-initialised weights.
+
+One step = one frame of the whole path: cull + splat + resolve (lnr_render),
+depth filter (lnr_depth_filter) and U-Net (lnr_reconstruct), with the cloud
+and weights already resident in HBM.  `value` is float32-U-Net frames/s; the
+bfloat16 modes are reported beside it with their error against the float64
+oracle on sampled windows.  Prints one JSON line on stdout.
+
+    python bench.py [--gpus 1] [--steps 120] [--warmup 10]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "frames/s and p50/p99 latency at 1080p/20M pts; BF16 vs FP32 U-Net at stated PSNR"
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+TOL = {"fp32": 1e-4, "bf16": 2e-2, "bf16x3": 2e-2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def conv_shapes(widths, H, W, cin0):
+    """(name, H_l, W_l, c_out, c_in) of every 3x3 convolution, with the logical c_in."""
+    L = len(widths)
+    out = []
+    for l in range(L):
+        out.append((f"conv/enc{l}a", H >> l, W >> l, widths[l], 5 if l == 0 else widths[l - 1]))
+        out.append((f"conv/enc{l}b", H >> l, W >> l, widths[l], widths[l]))
+    for l in range(L - 2, -1, -1):
+        out.append((f"conv/dec{l}a", H >> l, W >> l, widths[l], widths[l] + widths[l + 1]))
+        out.append((f"conv/dec{l}b", H >> l, W >> l, widths[l], widths[l]))
+    return out
+
+
+def algorithmic_bytes(H, W, n_levels, n_proc, n_filled, n_removed):
+    """Bytes each geometric kernel must move (reads + writes), per launch."""
+    P = H * W
+    sizes = [(H, W)]
+    for _ in range(n_levels):
+        h, w = sizes[-1]
+        sizes.append(((h + 1) // 2, (w + 1) // 2))
+    px = [h * w for h, w in sizes]
+    b = {
+        "clear": 8 * P,
+        "splat": 12 * n_proc,
+        "resolve": 8 * P + 8 * P + 4 * n_filled,
+        "pyramid": 8 * P + 4 * sum(px[1:]),
+    }
+    for k in range(n_levels - 1, 0, -1):
+        uc = px[k + 1] * (1 if k + 1 == n_levels else 2)
+        b[f"upsample/k{k}"] = 4 * px[k] + 4 * px[k + 1] + 4 * uc + 4 * px[k]
+    if n_levels:
+        uc = px[1] * (1 if n_levels == 1 else 2)
+        b["upsample/k0"] = 8 * P + 4 * px[1] + 4 * uc + 8 * n_removed
+    return b
+
+
+def host_info():
+    info = {"host": platform.node(), "nproc": os.cpu_count()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        info["rocm"] = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline(scene, cam, blob, n_levels, fs, widths):
+    """The CPU oracle as it stands, on a bounded sample of the workload."""
+    import numpy as np
+    from oracle import depth_filter as F
+    from oracle import grid as G
+    from oracle import render as R
+    from oracle import unet as U
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        blas_threads = 1
+    g = G.partition(scene.xyz, scene.rgb, 1.0)
+    t0 = time.perf_counter()
+    _, depth, rgba = R.render(g, cam)
+    H, W = cam.height, cam.width
+    fd, fr, _ = F.depth_filter(depth.reshape(H, W), rgba.reshape(H, W, 4), n_levels, fs)
+    t_geo = time.perf_counter() - t0
+    net = U.parse_blob(blob)
+    c = 128
+    y0, x0 = H // 2 - c // 2, W // 2 - c // 2
+    t0 = time.perf_counter()
+    U.forward(net, fd[y0:y0 + c, x0:x0 + c], fr[y0:y0 + c, x0:x0 + c])
+    t_unet_crop = time.perf_counter() - t0
+    t_unet = t_unet_crop * (H * W) / (c * c)
+    fps = 1.0 / (t_geo + t_unet)
+    return {
+        "value": round(fps, 6), "unit": "frames/s", "cores": int(blas_threads), "kind": "oracle",
+        "sample": (f"frame 0 of the path: oracle projection + resolve + depth filter over all {scene.n} points "
+                   f"({t_geo:.2f} s, single-threaded numpy), plus the float64 U-Net on a {c}x{c} crop "
+                   f"({t_unet_crop:.2f} s, BLAS threads {blas_threads}) scaled by pixel count to {W}x{H} "
+                   f"({t_unet:.1f} s)"),
+        "seconds_per_frame": round(t_geo + t_unet, 3),
+    }
+
+
+def sampled_error(fd, fr, blob, outs, H, W):
+    """max-abs and PSNR of each precision's output against the float64 oracle on
+    three 64x64 windows (centre, a corner, an edge), each computed on a crop
+    grown by the receptive margin so the values equal the full-frame ones."""
+    import numpy as np
+    from oracle import metrics as M
+    from oracle import unet as U
+    net = U.parse_blob(blob)
+    wins = [(H // 2 - 32, H // 2 + 32, W // 2 - 32, W // 2 + 32), (0, 64, 0, 64), (H - 64, H, W // 3, W // 3 + 64)]
+    refs = [U.forward_crop(net, fd, fr, *w) for w in wins]
+    res = {}
+    for name, y in outs.items():
+        got = np.concatenate([y[:, a:b, c:d].reshape(3, -1) for (a, b, c, d) in wins], axis=1)
+        ref = np.concatenate([r.reshape(3, -1) for r in refs], axis=1)
+        res[name] = {"max_abs": M.max_abs(got, ref), "psnr_db": round(M.psnr(got, ref), 2),
+                     "bound": TOL[name], "within_bound": bool(M.max_abs(got, ref) <= TOL[name])}
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=120)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--points", type=int, default=20_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precisions", default="fp32,bf16x3,bf16")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the path shards by frame and the "
+              "multi-GPU layout is described in DESIGN.md, not measured", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_11618_amd as L
+    import synth
+
+    W, H, FOV, NL, FS = 1920, 1080, 90.0, 5, 0.5
+    widths = (32, 64, 128, 256)
+    t0 = time.perf_counter()
+    scene = synth.scene_for_config("multiroom", seed=0, n_points=args.points)
+    log(f"scene {scene.name}: {scene.n} points ({time.perf_counter() - t0:.1f} s)")
+    cams = synth.orbit_path(scene, 120, W, H, FOV)
+    blob = synth.make_unet_blob(widths, seed=0)
+
+    torch.cuda.set_device(0)
+    ctx = L.lnr_context_create(0)
+    t0 = time.perf_counter()
+    cloud = L.lnr_cloud_load(ctx, scene.xyz, scene.rgb, 1.0)
+    load_s = time.perf_counter() - t0
+    info = L.lnr_cloud_info(cloud)
+    log(f"cloud loaded and partitioned in {load_s:.2f} s, grid {info['dims']}")
+    prec_ids = {"fp32": L.LNR_FP32, "bf16": L.LNR_BF16, "bf16x3": L.LNR_BF16X3}
+    precs = [p for p in args.precisions.split(",") if p]
+    nets = {p: L.lnr_unet_load(ctx, blob, prec_ids[p]) for p in precs}
+    img = L.Image(H, W)
+    out = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
+
+    def frame(i, net):
+        L.lnr_render(ctx, cloud, cams[i % len(cams)], img)
+        L.lnr_depth_filter(ctx, img, NL, FS)
+        L.lnr_reconstruct(ctx, net, img, out)
+
+    results = {}
+    kernel_stats = {}
+    for p in precs:
+        net = nets[p]
+        for i in range(args.warmup):
+            frame(i, net)
+        torch.cuda.synchronize()
+        # pass 1: frame rate and per-frame latency (one event pair per frame)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record()
+            frame(i, net)
+            ev[i][1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        # pass 2: the same frames with every kernel bracketed by events on its stream
+        L.lnr_profile_enable(ctx, True)
+        L.lnr_profile_read(ctx)
+        n_proc_total = 0
+        per_kernel = {}
+        for i in range(args.steps):
+            frame(i, net)
+            if p == precs[0]:
+                torch.cuda.synchronize()
+                vis, proc, _ = L.lnr_render_stats(ctx)
+                n_proc_total += proc
+            for name, ms in L.lnr_profile_read(ctx):
+                per_kernel.setdefault(name, []).append(ms)
+        L.lnr_profile_enable(ctx, False)
+        torch.cuda.synchronize()
+        results[p] = {
+            "frames_per_s": args.steps / wall,
+            "ms_per_frame": 1000.0 * wall / args.steps,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+        }
+        kernel_stats[p] = {k: (float(np.mean(v)), len(v)) for k, v in per_kernel.items()}
+        if p == precs[0]:
+            results[p]["processed_points_per_frame"] = n_proc_total / args.steps
+        log(f"{p}: {results[p]['frames_per_s']:.1f} frames/s, p50 {results[p]['latency_ms']['p50']:.2f} ms, "
+            f"p99 {results[p]['latency_ms']['p99']:.2f} ms")
+
+    # geometric-stage statistics of frame 0 (filled / removed pixels) for the byte counts
+    L.lnr_render(ctx, cloud, cams[0], img)
+    torch.cuda.synchronize()
+    _, proc0, _ = L.lnr_render_stats(ctx)
+    filled0 = int((img.rgba[..., 3] != 0).sum().item())
+    L.lnr_depth_filter(ctx, img, NL, FS)
+    torch.cuda.synchronize()
+    kept0 = int((img.rgba[..., 3] != 0).sum().item())
+    fd, fr = img.depth.cpu().numpy(), img.rgba.cpu().numpy()
+    outs = {}
+    for p in precs:
+        L.lnr_reconstruct(ctx, nets[p], img, out)
+        torch.cuda.synchronize()
+        outs[p] = out.cpu().numpy().astype(np.float64)
+    errors = sampled_error(fd, fr, blob, outs, H, W)
+
+    # rooflines
+    p0 = precs[0]
+    ks = kernel_stats[p0]
+    cin0 = 8
+    flops = {name: 2.0 * h * w * co * 9 * ci for (name, h, w, co, ci) in conv_shapes(widths, H, W, cin0)}
+    conv_ms = {k: v[0] for k, v in ks.items() if k.startswith("conv/")}
+    dom = max(conv_ms, key=conv_ms.get)
+    achieved = flops[dom] / (conv_ms[dom] * 1e-3) / 1e12
+    roofline = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["fp32"],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": None,
+                "flops_per_launch": flops[dom], "avg_launch_ms": round(conv_ms[dom], 4)}
+    unet_ms = sum(v[0] for k, v in ks.items() if k.startswith("conv/") or k in ("pack", "head"))
+    unet_flops = sum(flops.values()) + 2.0 * H * W * 3 * widths[0]
+    n_proc = results[p0].get("processed_points_per_frame", proc0)
+    gbytes = algorithmic_bytes(H, W, NL, n_proc, filled0, filled0 - kept0)
+    geo_names = [k for k in ks if k in gbytes]
+    geo_ms = sum(ks[k][0] for k in geo_names)
+    geo_bytes = sum(gbytes[k] for k in geo_names)
+    geo_gbs = geo_bytes / (geo_ms * 1e-3) / 1e9
+    splat_gbs = gbytes["splat"] / (ks["splat"][0] * 1e-3) / 1e9
+    rooflines = {
+        "unet_fp32_all_convs": {"bound": "mfma", "achieved": round(unet_flops / (unet_ms * 1e-3) / 1e12, 2),
+                                "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                                "frac": round(unet_flops / (unet_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4)},
+        "render_and_filter": {"bound": "hbm", "achieved": round(geo_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": round(geo_gbs / PEAK_HBM_GBS, 4), "bytes_per_frame": geo_bytes,
+                              "ms_per_frame": round(geo_ms, 4)},
+        "splat": {"bound": "hbm", "achieved": round(splat_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": round(splat_gbs / PEAK_HBM_GBS, 4), "points_per_launch": n_proc,
+                  "avg_launch_ms": round(ks["splat"][0], 4),
+                  "points_per_s": round(n_proc / (ks["splat"][0] * 1e-3), 1)},
+    }
+    for p in precs[1:]:
+        kp = kernel_stats[p]
+        ms = sum(v[0] for k, v in kp.items() if k.startswith("conv/") or k in ("pack", "head"))
+        mult = 3.0 if p == "bf16x3" else 1.0
+        rooflines[f"unet_{p}_all_convs"] = {
+            "bound": "mfma", "achieved": round(unet_flops / (ms * 1e-3) / 1e12, 2), "peak": PEAK_TFLOPS["bf16"],
+            "unit": "TFLOP/s", "frac": round(unet_flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"], 4),
+            "mfma_passes_per_product": mult}
+
+    fps = results[p0]["frames_per_s"]
+    line = {
+        "metric": METRIC,
+        "value": round(fps, 3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(results[p0]["ms_per_frame"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "multiroom-20M-pts-1920x1080-orbit120", "points": scene.n, "scans": 4,
+                   "cell_m": 1.0, "width": W, "height": H, "fov_deg": FOV, "n_levels": NL, "filter_strength": FS,
+                   "unet_widths": list(widths), "frames": len(cams), "grid_dims": list(info["dims"])},
+        "latency_ms": {k: round(v, 4) for k, v in results[p0]["latency_ms"].items()},
+        "points_per_s": round(n_proc * fps, 1),
+        "processed_points_per_frame": round(n_proc, 1),
+        "precisions": {p: {"frames_per_s": round(r["frames_per_s"], 3), "ms_per_frame": round(r["ms_per_frame"], 4),
+                           "latency_ms": {k: round(v, 4) for k, v in r["latency_ms"].items()},
+                           "error_vs_fp64_sampled": errors[p]} for p, r in results.items()},
+        "stage_ms": {p: {k: round(v[0], 4) for k, v in sorted(kernel_stats[p].items())} for p in precs},
+        "roofline": roofline,
+        "rooflines": rooflines,
+        "load_partition_s": round(load_s, 3),
+        "frame0": {"processed_points": proc0, "filled_pixels": filled0, "kept_after_filter": kept0},
+        "env": host_info(),
+    }
+    try:
+        line["env"]["gpu"] = torch.cuda.get_device_name(0)
+        line["env"]["cus"] = torch.cuda.get_device_properties(0).multi_processor_count
+    except Exception:
+        pass
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        line["cpu_baseline"] = cpu_baseline(scene, cams[0], blob, NL, FS, widths)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * lnr.h - C ABI of the MI355X (gfx950) per-frame rendering path of
+ * "Real-time Neural Rendering of LiDAR Point Clouds" (arXiv 2502.11618).
+ *
+ * The path (Fig. 1 of the paper): a coloured point cloud, partitioned once
+ * into a uniform grid, is frustum-culled per cell and projected as 1x1-pixel
+ * points into an RGB + depth + fill-mask image (RGBDA); a hierarchical
+ * min-pool depth filter removes background points that leak between
+ * foreground points (Fig. 2); a fully convolutional U-Net reconstructs the
+ * final RGB image.  Every stage runs in hand-written HIP kernels.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns lnr_status; on failure lnr_last_error() holds a
+ *     message.  Nothing crosses the ABI as an exception, abort or exit.
+ *   - Argument checks are synchronous: when a call fails them nothing is
+ *     enqueued and caller buffers are untouched.
+ *   - Device work is enqueued on the caller's HIP stream (`hip_stream`, a
+ *     hipStream_t passed as void*; NULL = the default stream) and returns
+ *     before it completes.  Kernel faults surface as LNR_E_DEVICE from a later
+ *     call or from lnr_sync().
+ *   - Pointers documented as DEVICE point to device memory the caller owns
+ *     and keeps alive until its stream work completes; HOST pointers are read
+ *     or written before the call returns.  The library never frees caller
+ *     memory.
+ *   - A context owns device scratch that every call on it reuses; a context is
+ *     externally synchronised and its calls must not overlap on different
+ *     streams (use one context per concurrent stream).  Clouds and networks
+ *     are read-only after loading and may be shared by contexts of the same
+ *     device.
+ */
+#ifndef LNR_H
+#define LNR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LNR_OK = 0,
+  LNR_E_INVALID_ARG = -1,   /* a pointer, size or value is out of range        */
+  LNR_E_OUT_OF_MEMORY = -2, /* hipMalloc failed                                  */
+  LNR_E_BUDGET = -3,        /* the allocation would exceed the context's budget  */
+  LNR_E_DEVICE = -4,        /* a HIP runtime call or kernel failed               */
+  LNR_E_UNSUPPORTED = -5,   /* a valid request this build does not handle        */
+  LNR_E_FORMAT = -6         /* a malformed weight blob                           */
+} lnr_status;
+
+typedef struct lnr_context lnr_context; /* device scratch, budget, last error       */
+typedef struct lnr_cloud lnr_cloud;     /* partitioned cloud, device-resident         */
+typedef struct lnr_unet lnr_unet;       /* U-Net weights repacked for one precision   */
+
+/* Pinhole camera.  P is the row-major 3x4 projection: for a world point X,
+ * (a, b, w) = P [X; 1]; w is the camera-space depth and (u, v) = (a/w, b/w)
+ * the image position, pixel (px, py) covering [px, px+1) x [py, py+1).
+ * A point is drawn iff z_near <= w <= z_far, 0 <= u < width, 0 <= v < height.
+ * Requires 1 <= width, height <= 16384, finite P, 0 < z_near < z_far. */
+typedef struct {
+  float P[12];
+  int32_t width, height;
+  float z_near, z_far;
+} lnr_camera;
+
+/* An RGBDA image: caller-owned DEVICE buffers, row-major, tightly packed.
+ *   key   : uint64[width*height]  z-buffer key (depth bits << 32 | point index);
+ *           0xFFFFFFFFFFFFFFFF = empty.  May be NULL for lnr_depth_filter and
+ *           lnr_reconstruct.
+ *   depth : float[width*height]   camera-space depth, 0 where empty.
+ *   rgba  : uint8[4*width*height] colour + fill mask A in {0, 1}; (0,0,0,0) where empty. */
+typedef struct {
+  uint64_t *key;
+  float *depth;
+  uint8_t *rgba;
+  int32_t width, height;
+} lnr_image;
+
+/* U-Net arithmetic.
+ *   LNR_FP32   : float32 activations, float32 matrix-core products.
+ *   LNR_BF16   : bfloat16 activations and weights, float32 accumulation.
+ *   LNR_BF16X3 : float32 activations; each operand split into bfloat16
+ *                high + low parts and multiplied as hi*hi + hi*lo + lo*hi
+ *                with float32 accumulation (near-float32 accuracy on
+ *                bfloat16 matrix cores). */
+typedef enum { LNR_FP32 = 0, LNR_BF16 = 1, LNR_BF16X3 = 2 } lnr_precision;
+
+/* lnr_render flag: visit every non-empty cell (no frustum test).  The result
+ * is identical; this exists to check that culling is a pure speed-up. */
+#define LNR_RENDER_NO_CULL 1u
+
+/* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the
+ * device memory the context, and the clouds and networks loaded through it,
+ * may allocate (0 = no cap). */
+lnr_status lnr_context_create(int hip_device, uint64_t hbm_budget_bytes, lnr_context **out);
+/* Free a context and its scratch.  NULL-safe.  Clouds and networks loaded
+ * through it must be destroyed first. */
+void lnr_context_destroy(lnr_context *ctx);
+/* Message of the last failure on ctx (valid until the next call on ctx);
+ * with ctx == NULL, the last failure of lnr_context_create. */
+const char *lnr_last_error(const lnr_context *ctx);
+/* Device bytes currently allocated through ctx (scratch, clouds, networks). */
+uint64_t lnr_allocated_bytes(const lnr_context *ctx);
+
+/* Load and partition a cloud (Method, "Point Cloud Projection": a uniform
+ * grid is the only preprocessing and enables view-frustum culling).
+ *   xyz_host : HOST float[n*3], interleaved x, y, z; must be finite.
+ *   rgb_host : HOST uint8[n*3].
+ *   1 <= n < 2^32; cell_size finite and > 0; at most 2^31 cells.
+ * The grid origin is the componentwise minimum of the points; per axis
+ * n_a = max(1, ceil((max_a - min_a) / cell_size)) cells, and a point's cell
+ * index is min(n_a - 1, floor((x_a - min_a) / cell_size)) evaluated in double.
+ * Points are stably sorted by cell id (z-major, then y, then x); a point's
+ * position in that order is its index in z-buffer keys.  Synchronous: the
+ * call returns after the device copy is built. */
+lnr_status lnr_cloud_load(lnr_context *ctx, const float *xyz_host, const uint8_t *rgb_host, uint64_t n,
+                          float cell_size, lnr_cloud **out);
+/* Grid geometry of a loaded cloud (any output pointer may be NULL). */
+lnr_status lnr_cloud_info(const lnr_cloud *c, uint64_t *n, int32_t dims[3], float origin[3], float *cell_size);
+/* HOST uint32[n]: sorted position -> input index. */
+lnr_status lnr_cloud_permutation(const lnr_cloud *c, uint32_t *perm_host);
+/* HOST uint32[n_cells + 1]: exclusive prefix of the per-cell point counts. */
+lnr_status lnr_cloud_cell_start(const lnr_cloud *c, uint32_t *cell_start_host);
+void lnr_cloud_destroy(lnr_cloud *c);
+
+/* Render one view into `out` (Fig. 1, projection stage): cull grid cells
+ * against the frustum, project each point of the surviving cells to one pixel
+ * and keep, per pixel, the point with the smallest key
+ * (float32 depth bits << 32 | sorted index): the nearest point, ties to the
+ * lowest index.  Then write depth and rgba = (r, g, b, 1) of the winner, or
+ * 0 / (0,0,0,0) for empty pixels.  Per point, in float32 without fused
+ * multiply-add: a = ((P0 x + P1 y) + P2 z) + P3, b and w likewise,
+ * u = a / w, v = b / w (correctly rounded).  A cell is skipped only if no
+ * point in it can pass the per-point test (float64 bound with slack), so
+ * culling never changes the image.  out->key, depth and rgba must all be
+ * non-NULL with out->width/height equal to the camera's.  flags: 0 or
+ * LNR_RENDER_NO_CULL. */
+lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out, uint32_t flags,
+                      void *hip_stream);
+/* Statistics of the last lnr_render on ctx; waits for ctx's last stream.
+ * visible_cells: cells that passed the frustum test; processed_points:
+ * points in those cells.  cull_flags_host (may be NULL): HOST uint8[n_cells]
+ * of the cloud last rendered, 1 = visible. */
+lnr_status lnr_render_stats(lnr_context *ctx, uint64_t *visible_cells, uint64_t *processed_points,
+                            uint8_t *cull_flags_host);
+
+/* Depth filter, in place (Method, "Depth filtering" and Fig. 2): min-pool the
+ * depth n_levels times (2x2, stride 2, empty = +inf), then upsample level by
+ * level: a 4-neighbour Laplacian on the coarser min-pooled level marks edges;
+ * each child is kept iff its depth <= ref * (1 + filter_strength), where ref
+ * is the parent's upsampled depth, or at edges the maximum over the parent's
+ * 3x3 neighbourhood; rejected pixels of non-final levels are refilled by
+ * bilinear interpolation of the coarser level.  Removed pixels become depth
+ * 0, rgba (0,0,0,0); kept pixels are unchanged; `key` is not read or written.
+ * 0 <= n_levels <= floor(log2(min(width, height))); filter_strength >= 0 and
+ * not NaN (+inf keeps everything). */
+lnr_status lnr_depth_filter(lnr_context *ctx, lnr_image *inout, int32_t n_levels, float filter_strength,
+                            void *hip_stream);
+
+/* Load U-Net weights (Fig. 1; Method, "U-Net Reconstruction") from a HOST
+ * blob (layout: magic "LNRU", u32 version 1|2, u32 levels L, in_channels (5),
+ * out_channels (3), widths[L], then 4L-1 conv records enc0a, enc0b, ...,
+ * dec0b, head, each u32 c_out, c_in, k, [u32 has_bn if version 2], f32 OIHW
+ * weights, f32 bias, [f32 gamma, beta, mean, var per channel and f32 eps if
+ * has_bn]).  Batch norm is folded into its convolution.  Supported: 1 <= L
+ * <= 6, widths multiples of 16 up to 512, 3x3 convs and a 1x1 head.
+ * Synchronous. */
+lnr_status lnr_unet_load(lnr_context *ctx, const void *blob_host, uint64_t bytes, lnr_precision prec,
+                         lnr_unet **out);
+void lnr_unet_destroy(lnr_unet *u);
+/* Forward pass on an RGBDA image.  Input x = (r/255, g/255, b/255,
+ * A ? D/16 : 0, A); per level two 3x3 conv + bias + ReLU, 2x2 max-pool
+ * between encoder levels, nearest x2 upsample and concatenation
+ * [skip, upsampled] in the decoder, 1x1 head without activation.
+ * rgb_out: DEVICE float[3*H*W], planar.  Requires H and W divisible by
+ * 2^(L-1). */
+lnr_status lnr_reconstruct(lnr_context *ctx, const lnr_unet *u, const lnr_image *in, float *rgb_out,
+                           void *hip_stream);
+
+/* Wait for `hip_stream` and report any pending device error. */
+lnr_status lnr_sync(lnr_context *ctx, void *hip_stream);
+
+/* Kernel timing.  While enabled, every kernel a call on ctx enqueues is
+ * bracketed by HIP events on the same stream, and lnr_profile_read returns
+ * (and forgets) the launches recorded since the last read, oldest first:
+ * name (static string, e.g. "splat", "conv/dec0a"), duration in ms.  It waits
+ * for the recorded work.  At most `max` records are copied; *count receives
+ * the number recorded (records past `max` are dropped).  Disabled by default;
+ * enabling adds two event records per launch. */
+typedef struct {
+  const char *name;
+  float ms;
+} lnr_kernel_time;
+lnr_status lnr_profile_enable(lnr_context *ctx, int enable);
+lnr_status lnr_profile_read(lnr_context *ctx, lnr_kernel_time *out, int32_t max, int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LNR_H */

@@ -1,0 +1,850 @@
+// Host runtime behind the C ABI declared in include/lnr.h: argument checks,
+// device memory and budget accounting, weight repacking, and the enqueueing
+// of the HIP kernels that make up each stage.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "lnr_internal.h"
+
+using namespace lnr;
+
+namespace {
+
+struct Buf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct lnr_context {
+  int device = 0;
+  uint64_t budget = 0;
+  uint64_t allocated = 0;
+  std::string err;
+  hipStream_t last_stream = nullptr;
+  bool rendered = false;
+  uint32_t last_cells = 0;
+  Buf flags, chunks, counters, pyramid, act;
+  // kernel timing
+  struct Rec {
+    const char *name;
+    hipEvent_t a, b;
+  };
+  bool profiling = false;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> event_pool;
+};
+
+struct lnr_cloud {
+  lnr_context *ctx = nullptr;
+  CloudDev d;
+  std::vector<std::pair<void *, size_t>> allocs;
+};
+
+struct lnr_unet {
+  lnr_context *ctx = nullptr;
+  Prec prec = Prec::F32;
+  int L = 0;
+  int widths[6] = {0, 0, 0, 0, 0, 0};
+  int cin0_pad = 8;
+  std::vector<ConvLayer> convs;  // 4L - 2 3x3 convolutions in network order
+  ConvLayer head;
+  std::vector<std::pair<void *, size_t>> allocs;
+};
+
+namespace {
+
+lnr_status fail(lnr_context *ctx, lnr_status st, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+lnr_status hip_fail(lnr_context *ctx, hipError_t e, const char *what) {
+  return fail(ctx, LNR_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define LNR_HIP(ctx, expr)                                 \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+hipEvent_t get_event(lnr_context *ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Enqueue one launcher; with timing enabled, bracket it by events on the same stream.
+#define LNR_LAUNCH(ctx, nm, s, expr)                                            \
+  do {                                                                          \
+    hipEvent_t a_ = nullptr, b_ = nullptr;                                      \
+    if ((ctx)->profiling) {                                                     \
+      a_ = get_event(ctx);                                                      \
+      b_ = get_event(ctx);                                                      \
+      if (a_) (void)hipEventRecord(a_, s);                                      \
+    }                                                                           \
+    hipError_t e_ = (expr);                                                     \
+    if (a_ && b_) {                                                             \
+      (void)hipEventRecord(b_, s);                                              \
+      (ctx)->recs.push_back({nm, a_, b_});                                      \
+    }                                                                           \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, nm);                         \
+  } while (0)
+
+const char *const kUpsampleNames[16] = {"upsample/k0",  "upsample/k1",  "upsample/k2",  "upsample/k3",
+                                        "upsample/k4",  "upsample/k5",  "upsample/k6",  "upsample/k7",
+                                        "upsample/k8",  "upsample/k9",  "upsample/k10", "upsample/k11",
+                                        "upsample/k12", "upsample/k13", "upsample/k14", "upsample/k15"};
+const char *const kConvNames[2][6][2] = {
+    {{"conv/enc0a", "conv/enc0b"}, {"conv/enc1a", "conv/enc1b"}, {"conv/enc2a", "conv/enc2b"},
+     {"conv/enc3a", "conv/enc3b"}, {"conv/enc4a", "conv/enc4b"}, {"conv/enc5a", "conv/enc5b"}},
+    {{"conv/dec0a", "conv/dec0b"}, {"conv/dec1a", "conv/dec1b"}, {"conv/dec2a", "conv/dec2b"},
+     {"conv/dec3a", "conv/dec3b"}, {"conv/dec4a", "conv/dec4b"}, {"conv/dec5a", "conv/dec5b"}}};
+
+lnr_status dalloc(lnr_context *ctx, void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (ctx->budget && ctx->allocated + bytes > ctx->budget)
+    return fail(ctx, LNR_E_BUDGET,
+                "allocation of " + std::to_string(bytes) + " bytes exceeds the context budget of " +
+                    std::to_string(ctx->budget) + " bytes (" + std::to_string(ctx->allocated) + " in use)");
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(ctx, LNR_E_OUT_OF_MEMORY, "hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e));
+  }
+  ctx->allocated += bytes;
+  return LNR_OK;
+}
+
+void dfree(lnr_context *ctx, void *p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  if (bytes == 0) bytes = 256;
+  ctx->allocated -= std::min<uint64_t>(ctx->allocated, bytes);
+}
+
+// grow-only scratch; an old buffer is released only after the device is idle
+lnr_status ensure(lnr_context *ctx, Buf &b, size_t bytes) {
+  if (b.cap >= bytes && b.p) return LNR_OK;
+  if (b.p) {
+    LNR_HIP(ctx, hipDeviceSynchronize());
+    dfree(ctx, b.p, b.cap);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  lnr_status st = dalloc(ctx, &b.p, bytes);
+  if (st == LNR_OK) b.cap = bytes;
+  return st;
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+lnr_status use_device(lnr_context *ctx) {
+  LNR_HIP(ctx, hipSetDevice(ctx->device));
+  return LNR_OK;
+}
+
+template <typename T>
+lnr_status cloud_alloc(lnr_cloud *c, T **p, size_t count) {
+  void *v = nullptr;
+  lnr_status st = dalloc(c->ctx, &v, count * sizeof(T));
+  if (st != LNR_OK) return st;
+  c->allocs.emplace_back(v, count * sizeof(T) ? count * sizeof(T) : 256);
+  *p = static_cast<T *>(v);
+  return LNR_OK;
+}
+
+void cloud_free(lnr_cloud *c) {
+  for (auto &a : c->allocs) dfree(c->ctx, a.first, a.second);
+  c->allocs.clear();
+}
+
+struct TempAllocs {
+  lnr_context *ctx;
+  std::vector<std::pair<void *, size_t>> v;
+  explicit TempAllocs(lnr_context *c) : ctx(c) {}
+  ~TempAllocs() {
+    for (auto &a : v) dfree(ctx, a.first, a.second);
+  }
+  template <typename T>
+  lnr_status get(T **p, size_t bytes) {
+    void *q = nullptr;
+    lnr_status st = dalloc(ctx, &q, bytes);
+    if (st != LNR_OK) return st;
+    v.emplace_back(q, bytes ? bytes : 256);
+    *p = static_cast<T *>(q);
+    return LNR_OK;
+  }
+};
+
+bool camera_ok(const lnr_camera *cam, std::string *why) {
+  for (int i = 0; i < 12; ++i)
+    if (!std::isfinite(cam->P[i])) {
+      *why = "camera P must be finite";
+      return false;
+    }
+  if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384) {
+    *why = "camera width/height must be in [1, 16384]";
+    return false;
+  }
+  if (!(std::isfinite(cam->z_near) && std::isfinite(cam->z_far) && cam->z_near > 0.f && cam->z_near < cam->z_far)) {
+    *why = "camera needs finite 0 < z_near < z_far";
+    return false;
+  }
+  return true;
+}
+
+// Frustum half-spaces of the per-point test, in double, in a fixed order of
+// operations (the order defines the exact cull decision).
+CullParams make_cull_params(const lnr_camera *cam, bool no_cull) {
+  CullParams p{};
+  double P[3][4];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 4; ++k) P[r][k] = (double)cam->P[4 * r + k];
+  const double *a = P[0], *b = P[1], *w = P[2];
+  const double n64 = (double)cam->z_near, f64 = (double)cam->z_far;
+  const double Wd = (double)cam->width, Hd = (double)cam->height;
+  const double hs[6][4] = {
+      {w[0], w[1], w[2], w[3] - n64},
+      {-w[0], -w[1], -w[2], f64 - w[3]},
+      {a[0], a[1], a[2], a[3]},
+      {Wd * w[0] - a[0], Wd * w[1] - a[1], Wd * w[2] - a[2], Wd * w[3] - a[3]},
+      {b[0], b[1], b[2], b[3]},
+      {Hd * w[0] - b[0], Hd * w[1] - b[1], Hd * w[2] - b[2], Hd * w[3] - b[3]},
+  };
+  std::memcpy(p.hs, hs, sizeof(hs));
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 4; ++k) p.absP[r][k] = std::fabs(P[r][k]);
+  p.wh1 = (Wd + Hd) + 1.0;
+  p.no_cull = no_cull ? 1 : 0;
+  return p;
+}
+
+uint16_t host_f2bf(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float host_bf2f(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+}  // namespace
+
+extern "C" {
+
+lnr_status lnr_context_create(int hip_device, uint64_t hbm_budget_bytes, lnr_context **out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return LNR_E_INVALID_ARG;
+  }
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) {
+    g_create_error = std::string("no HIP device available: ") + hipGetErrorString(e);
+    return LNR_E_DEVICE;
+  }
+  if (hip_device < 0 || hip_device >= count) {
+    g_create_error = "hip_device out of range";
+    return LNR_E_INVALID_ARG;
+  }
+  e = hipSetDevice(hip_device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+    return LNR_E_DEVICE;
+  }
+  auto *ctx = new (std::nothrow) lnr_context;
+  if (!ctx) {
+    g_create_error = "out of host memory";
+    return LNR_E_OUT_OF_MEMORY;
+  }
+  ctx->device = hip_device;
+  ctx->budget = hbm_budget_bytes;
+  *out = ctx;
+  return LNR_OK;
+}
+
+void lnr_context_destroy(lnr_context *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (Buf *b : {&ctx->flags, &ctx->chunks, &ctx->counters, &ctx->pyramid, &ctx->act}) dfree(ctx, b->p, b->cap);
+  for (auto &r : ctx->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+const char *lnr_last_error(const lnr_context *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+uint64_t lnr_allocated_bytes(const lnr_context *ctx) { return ctx ? ctx->allocated : 0; }
+
+// ---------------------------------------------------------------------------
+// cloud
+// ---------------------------------------------------------------------------
+static lnr_status cloud_build(lnr_context *ctx, lnr_cloud *c, const float *xyz_host, const uint8_t *rgb_host,
+                              uint32_t N, float cell_size);
+
+lnr_status lnr_cloud_load(lnr_context *ctx, const float *xyz_host, const uint8_t *rgb_host, uint64_t n,
+                          float cell_size, lnr_cloud **out) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!xyz_host || !rgb_host || !out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
+  *out = nullptr;
+  if (n < 1 || n >= (1ull << 32)) return fail(ctx, LNR_E_INVALID_ARG, "n must be in [1, 2^32)");
+  if (!(std::isfinite(cell_size) && cell_size > 0.f))
+    return fail(ctx, LNR_E_INVALID_ARG, "cell_size must be finite and > 0");
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  std::unique_ptr<lnr_cloud> c(new lnr_cloud);
+  c->ctx = ctx;
+  st = cloud_build(ctx, c.get(), xyz_host, rgb_host, (uint32_t)n, cell_size);
+  if (st != LNR_OK) {
+    (void)hipDeviceSynchronize();
+    cloud_free(c.get());
+    return st;
+  }
+  *out = c.release();
+  return LNR_OK;
+}
+
+static lnr_status cloud_build(lnr_context *ctx, lnr_cloud *cl, const float *xyz_host, const uint8_t *rgb_host,
+                              uint32_t N, float cell_size) {
+  lnr_cloud *c = cl;
+  lnr_status st;
+  hipStream_t s = nullptr;
+  TempAllocs tmp(ctx);
+  float *d_xyz;
+  uint8_t *d_rgb;
+  if ((st = tmp.get(&d_xyz, 12ull * N)) != LNR_OK) return st;
+  if ((st = tmp.get(&d_rgb, 3ull * N)) != LNR_OK) return st;
+  LNR_HIP(ctx, hipMemcpy(d_xyz, xyz_host, 12ull * N, hipMemcpyHostToDevice));
+  LNR_HIP(ctx, hipMemcpy(d_rgb, rgb_host, 3ull * N, hipMemcpyHostToDevice));
+
+  // bounding box + finiteness
+  const uint32_t nb = bbox_blocks(N);
+  float *d_part;
+  if ((st = tmp.get(&d_part, 7ull * nb * 4)) != LNR_OK) return st;
+  LNR_HIP(ctx, launch_bbox(d_xyz, N, d_part, nb, s));
+  std::vector<float> part(7ull * nb);
+  LNR_HIP(ctx, hipMemcpy(part.data(), d_part, part.size() * 4, hipMemcpyDeviceToHost));
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (uint32_t b = 0; b < nb; ++b) {
+    if (part[7 * b + 6] != 0.f) return fail(ctx, LNR_E_INVALID_ARG, "xyz contains non-finite values");
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], part[7 * b + a]);
+      hi[a] = std::max(hi[a], part[7 * b + 3 + a]);
+    }
+  }
+  const double s64 = (double)cell_size;
+  uint64_t C = 1;
+  for (int a = 0; a < 3; ++a) {
+    const double ext = (double)hi[a] - (double)lo[a];
+    const double na = std::max(1.0, std::ceil(ext / s64));
+    if (na > 2147483648.0) return fail(ctx, LNR_E_INVALID_ARG, "grid has more than 2^31 cells");
+    c->d.dims[a] = (int32_t)na;
+    C *= (uint64_t)na;
+    if (C > (1ull << 31)) return fail(ctx, LNR_E_INVALID_ARG, "grid has more than 2^31 cells");
+    c->d.origin[a] = lo[a];
+  }
+  c->d.n = N;
+  c->d.n_cells = (uint32_t)C;
+  c->d.cell_size = cell_size;
+
+  // cell ids, stable sort by cell
+  uint32_t *keys, *vals, *keys_alt, *vals_alt;
+  void *sort_scratch;
+  if ((st = tmp.get(&keys, 4ull * N)) != LNR_OK) return st;
+  if ((st = tmp.get(&keys_alt, 4ull * N)) != LNR_OK) return st;
+  if ((st = tmp.get(&vals_alt, 4ull * N)) != LNR_OK) return st;
+  if ((st = tmp.get(&sort_scratch, radix_sort_scratch_bytes(N))) != LNR_OK) return st;
+  if ((st = cloud_alloc(c, &vals, N)) != LNR_OK) return st;  // becomes perm (may swap below)
+  const double lo64[3] = {(double)lo[0], (double)lo[1], (double)lo[2]};
+  LNR_HIP(ctx, launch_cell_ids(d_xyz, N, lo64, s64, c->d.dims, keys, s));
+  LNR_HIP(ctx, launch_iota(vals, N, s));
+  int bits = 0;
+  while (bits < 32 && ((uint64_t)(C - 1) >> bits) != 0) ++bits;
+  uint32_t *k_sorted = keys, *v_sorted = vals, *k_alt = keys_alt, *v_alt = vals_alt;
+  LNR_HIP(ctx, radix_sort_pairs(&k_sorted, &v_sorted, &k_alt, &v_alt, N, bits, sort_scratch, s));
+  if (v_sorted != vals) {
+    // the sorted permutation ended in the temporary buffer: copy it into the cloud's buffer
+    LNR_HIP(ctx, hipMemcpyAsync(vals, v_sorted, 4ull * N, hipMemcpyDeviceToDevice, s));
+  }
+  c->d.perm = vals;
+
+  if ((st = cloud_alloc(c, &c->d.cell_start, (size_t)C + 1)) != LNR_OK) return st;
+  LNR_HIP(ctx, launch_cell_bounds(k_sorted, N, (uint32_t)C, c->d.cell_start, s));
+  if ((st = cloud_alloc(c, &c->d.x, N)) != LNR_OK) return st;
+  if ((st = cloud_alloc(c, &c->d.y, N)) != LNR_OK) return st;
+  if ((st = cloud_alloc(c, &c->d.z, N)) != LNR_OK) return st;
+  if ((st = cloud_alloc(c, &c->d.rgbx, N)) != LNR_OK) return st;
+  LNR_HIP(ctx, launch_gather_points(d_xyz, d_rgb, c->d.perm, N, c->d.x, c->d.y, c->d.z, c->d.rgbx, s));
+  if ((st = cloud_alloc(c, &c->d.aabb, 6 * (size_t)C)) != LNR_OK) return st;
+  LNR_HIP(ctx, launch_cell_aabb(c->d.x, c->d.y, c->d.z, c->d.cell_start, (uint32_t)C, c->d.aabb, s));
+  uint32_t *d_total;
+  if ((st = tmp.get(&d_total, 256)) != LNR_OK) return st;
+  LNR_HIP(ctx, hipMemsetAsync(d_total, 0, 4, s));
+  LNR_HIP(ctx, launch_chunk_count(c->d.cell_start, (uint32_t)C, d_total, s));
+  uint32_t total = 0;
+  LNR_HIP(ctx, hipMemcpy(&total, d_total, 4, hipMemcpyDeviceToHost));
+  LNR_HIP(ctx, hipDeviceSynchronize());
+  c->d.max_chunks = total;
+  return LNR_OK;
+}
+
+lnr_status lnr_cloud_info(const lnr_cloud *c, uint64_t *n, int32_t dims[3], float origin[3], float *cell_size) {
+  if (!c) return LNR_E_INVALID_ARG;
+  if (n) *n = c->d.n;
+  if (dims)
+    for (int a = 0; a < 3; ++a) dims[a] = c->d.dims[a];
+  if (origin)
+    for (int a = 0; a < 3; ++a) origin[a] = c->d.origin[a];
+  if (cell_size) *cell_size = c->d.cell_size;
+  return LNR_OK;
+}
+
+lnr_status lnr_cloud_permutation(const lnr_cloud *c, uint32_t *perm_host) {
+  if (!c || !perm_host) return LNR_E_INVALID_ARG;
+  lnr_context *ctx = c->ctx;
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  LNR_HIP(ctx, hipMemcpy(perm_host, c->d.perm, 4ull * c->d.n, hipMemcpyDeviceToHost));
+  return LNR_OK;
+}
+
+lnr_status lnr_cloud_cell_start(const lnr_cloud *c, uint32_t *cell_start_host) {
+  if (!c || !cell_start_host) return LNR_E_INVALID_ARG;
+  lnr_context *ctx = c->ctx;
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  LNR_HIP(ctx, hipMemcpy(cell_start_host, c->d.cell_start, 4ull * (c->d.n_cells + 1ull), hipMemcpyDeviceToHost));
+  return LNR_OK;
+}
+
+void lnr_cloud_destroy(lnr_cloud *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->ctx->device);
+  (void)hipDeviceSynchronize();
+  cloud_free(c);
+  delete c;
+}
+
+// ---------------------------------------------------------------------------
+// render
+// ---------------------------------------------------------------------------
+lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out, uint32_t flags,
+                      void *hip_stream) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!c || !cam || !out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
+  if (flags & ~LNR_RENDER_NO_CULL) return fail(ctx, LNR_E_INVALID_ARG, "unknown render flags");
+  std::string why;
+  if (!camera_ok(cam, &why)) return fail(ctx, LNR_E_INVALID_ARG, why);
+  if (!out->key || !out->depth || !out->rgba) return fail(ctx, LNR_E_INVALID_ARG, "image buffers must be non-NULL");
+  if (out->width != cam->width || out->height != cam->height)
+    return fail(ctx, LNR_E_INVALID_ARG, "image size differs from the camera's");
+  if (!aligned(out->key, 8) || !aligned(out->depth, 4) || !aligned(out->rgba, 4))
+    return fail(ctx, LNR_E_INVALID_ARG, "image buffers are misaligned");
+  if (c->ctx->device != ctx->device) return fail(ctx, LNR_E_INVALID_ARG, "cloud lives on another device");
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((st = ensure(ctx, ctx->flags, c->d.n_cells)) != LNR_OK) return st;
+  if ((st = ensure(ctx, ctx->chunks, 8ull * std::max<uint32_t>(1, c->d.max_chunks))) != LNR_OK) return st;
+  if ((st = ensure(ctx, ctx->counters, 256)) != LNR_OK) return st;
+  const uint32_t npix = (uint32_t)cam->width * (uint32_t)cam->height;
+  uint32_t *counters = static_cast<uint32_t *>(ctx->counters.p);
+  const CullParams prm = make_cull_params(cam, (flags & LNR_RENDER_NO_CULL) != 0);
+  SplatCam sc{};
+  std::memcpy(sc.P, cam->P, sizeof(sc.P));
+  sc.Wf = (float)cam->width;
+  sc.Hf = (float)cam->height;
+  sc.z_near = cam->z_near;
+  sc.z_far = cam->z_far;
+  sc.W = (uint32_t)cam->width;
+  LNR_LAUNCH(ctx, "clear", s, launch_clear(out->key, npix, counters, s));
+  LNR_LAUNCH(ctx, "cull", s, launch_cull(c->d, prm, static_cast<uint8_t *>(ctx->flags.p), static_cast<uint2 *>(ctx->chunks.p),
+                           counters, s));
+  LNR_LAUNCH(ctx, "splat", s, launch_splat(c->d, static_cast<const uint2 *>(ctx->chunks.p), counters, sc, out->key, s));
+  LNR_LAUNCH(ctx, "resolve", s, launch_resolve(out->key, c->d.rgbx, out->depth, reinterpret_cast<uint32_t *>(out->rgba), npix, s));
+  ctx->last_stream = s;
+  ctx->rendered = true;
+  ctx->last_cells = c->d.n_cells;
+  return LNR_OK;
+}
+
+lnr_status lnr_render_stats(lnr_context *ctx, uint64_t *visible_cells, uint64_t *processed_points,
+                            uint8_t *cull_flags_host) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!ctx->rendered) return fail(ctx, LNR_E_INVALID_ARG, "no render on this context yet");
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  LNR_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
+  uint32_t cnt[kCounterWords];
+  LNR_HIP(ctx, hipMemcpy(cnt, ctx->counters.p, sizeof(cnt), hipMemcpyDeviceToHost));
+  if (visible_cells) *visible_cells = cnt[1];
+  if (processed_points) *processed_points = (uint64_t)cnt[2] | ((uint64_t)cnt[3] << 32);
+  if (cull_flags_host)
+    LNR_HIP(ctx, hipMemcpy(cull_flags_host, ctx->flags.p, ctx->last_cells, hipMemcpyDeviceToHost));
+  return LNR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// depth filter
+// ---------------------------------------------------------------------------
+lnr_status lnr_depth_filter(lnr_context *ctx, lnr_image *io, int32_t n_levels, float filter_strength,
+                            void *hip_stream) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!io || !io->depth || !io->rgba) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
+  if (io->width < 1 || io->height < 1 || io->width > 16384 || io->height > 16384)
+    return fail(ctx, LNR_E_INVALID_ARG, "image width/height must be in [1, 16384]");
+  if (!aligned(io->depth, 4) || !aligned(io->rgba, 4)) return fail(ctx, LNR_E_INVALID_ARG, "misaligned buffers");
+  int maxn = 0;
+  while ((2 << maxn) <= std::min(io->width, io->height)) ++maxn;
+  if (n_levels < 0 || n_levels > maxn)
+    return fail(ctx, LNR_E_INVALID_ARG, "n_levels must be in [0, floor(log2(min(W, H)))]");
+  if (std::isnan(filter_strength) || filter_strength < 0.f)
+    return fail(ctx, LNR_E_INVALID_ARG, "filter_strength must be >= 0 and not NaN");
+  if (n_levels == 0) return LNR_OK;
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  int Hs[32], Ws[32];
+  Hs[0] = io->height;
+  Ws[0] = io->width;
+  size_t total = 0, offs[32];
+  for (int k = 1; k <= n_levels; ++k) {
+    Hs[k] = (Hs[k - 1] + 1) / 2;
+    Ws[k] = (Ws[k - 1] + 1) / 2;
+  }
+  // D[1..n] then U[1..n-1], each 256-byte aligned
+  for (int k = 1; k <= n_levels; ++k) {
+    offs[k] = total;
+    total += ((size_t)Hs[k] * Ws[k] * 4 + 255) / 256 * 256;
+  }
+  size_t uoffs[32];
+  for (int k = 1; k < n_levels; ++k) {
+    uoffs[k] = total;
+    total += ((size_t)Hs[k] * Ws[k] * 4 + 255) / 256 * 256;
+  }
+  if ((st = ensure(ctx, ctx->pyramid, total)) != LNR_OK) return st;
+  char *base = static_cast<char *>(ctx->pyramid.p);
+  float *D[32] = {nullptr}, *U[32] = {nullptr};
+  for (int k = 1; k <= n_levels; ++k) D[k] = reinterpret_cast<float *>(base + offs[k]);
+  for (int k = 1; k < n_levels; ++k) U[k] = reinterpret_cast<float *>(base + uoffs[k]);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  uint32_t *rgba = reinterpret_cast<uint32_t *>(io->rgba);
+  LNR_LAUNCH(ctx, "pyramid", s, launch_pyramid(io->depth, rgba, io->height, io->width, n_levels, D, s));
+  const float one_plus_fs = 1.0f + filter_strength;
+  for (int k = n_levels - 1; k >= 0; --k)
+    LNR_LAUNCH(ctx, kUpsampleNames[k & 15], s, launch_upsample(k, n_levels, D, U, Hs, Ws, io->depth, rgba, filter_strength, one_plus_fs, s));
+  ctx->last_stream = s;
+  return LNR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// U-Net
+// ---------------------------------------------------------------------------
+lnr_status lnr_unet_load(lnr_context *ctx, const void *blob_host, uint64_t bytes, lnr_precision prec,
+                         lnr_unet **out) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!blob_host || !out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
+  *out = nullptr;
+  if (prec != LNR_FP32 && prec != LNR_BF16 && prec != LNR_BF16X3)
+    return fail(ctx, LNR_E_INVALID_ARG, "unknown precision");
+  const uint8_t *p = static_cast<const uint8_t *>(blob_host);
+  size_t off = 0;
+  auto rd_u32 = [&](uint32_t *v) -> bool {
+    if (off + 4 > bytes) return false;
+    std::memcpy(v, p + off, 4);
+    off += 4;
+    return true;
+  };
+  if (bytes < 20 || std::memcmp(p, "LNRU", 4) != 0) return fail(ctx, LNR_E_FORMAT, "bad magic");
+  off = 4;
+  uint32_t version, L, in_ch, out_ch;
+  rd_u32(&version);
+  rd_u32(&L);
+  rd_u32(&in_ch);
+  rd_u32(&out_ch);
+  if (version != 1 && version != 2) return fail(ctx, LNR_E_FORMAT, "unknown version");
+  if (L < 1 || L > 6) return fail(ctx, LNR_E_UNSUPPORTED, "levels must be in [1, 6]");
+  if (in_ch != 5 || out_ch != 3) return fail(ctx, LNR_E_UNSUPPORTED, "network must map 5 to 3 channels");
+  std::unique_ptr<lnr_unet> u(new lnr_unet);
+  u->ctx = ctx;
+  u->L = (int)L;
+  u->prec = static_cast<Prec>(prec);
+  for (uint32_t l = 0; l < L; ++l) {
+    uint32_t w;
+    if (!rd_u32(&w)) return fail(ctx, LNR_E_FORMAT, "truncated header");
+    if (w < 16 || w > 512 || w % 16) return fail(ctx, LNR_E_UNSUPPORTED, "widths must be multiples of 16 in [16, 512]");
+    u->widths[l] = (int)w;
+  }
+  u->cin0_pad = (u->prec == Prec::F32) ? 8 : 16;
+  // expected (c_out, c_in, k) in blob order
+  std::vector<int> exp;
+  for (int l = 0; l < (int)L; ++l) {
+    const int ci = l == 0 ? 5 : u->widths[l - 1];
+    exp.insert(exp.end(), {u->widths[l], ci, 3, u->widths[l], u->widths[l], 3});
+  }
+  for (int l = (int)L - 2; l >= 0; --l)
+    exp.insert(exp.end(), {u->widths[l], u->widths[l] + u->widths[l + 1], 3, u->widths[l], u->widths[l], 3});
+  exp.insert(exp.end(), {3, u->widths[0], 1});
+  const int nconv = 4 * (int)L - 1;
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  auto free_all = [&]() {
+    for (auto &a : u->allocs) dfree(ctx, a.first, a.second);
+    u->allocs.clear();
+  };
+  auto upload = [&](const void *src, size_t nbytes, void **dst) -> lnr_status {
+    lnr_status s2 = dalloc(ctx, dst, nbytes);
+    if (s2 != LNR_OK) return s2;
+    u->allocs.emplace_back(*dst, nbytes);
+    hipError_t e = hipMemcpy(*dst, src, nbytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(weights)");
+    return LNR_OK;
+  };
+  for (int li = 0; li < nconv; ++li) {
+    uint32_t co, ci, k, has_bn = 0;
+    if (!rd_u32(&co) || !rd_u32(&ci) || !rd_u32(&k) || (version == 2 && !rd_u32(&has_bn))) {
+      free_all();
+      return fail(ctx, LNR_E_FORMAT, "truncated record header");
+    }
+    if ((int)co != exp[3 * li] || (int)ci != exp[3 * li + 1] || (int)k != exp[3 * li + 2]) {
+      free_all();
+      return fail(ctx, LNR_E_FORMAT, "conv record " + std::to_string(li) + " has an unexpected shape");
+    }
+    const size_t nw = (size_t)co * ci * k * k;
+    size_t need = 4 * (nw + co) + (has_bn ? 16ull * co + 4 : 0);
+    if (off + need > bytes) {
+      free_all();
+      return fail(ctx, LNR_E_FORMAT, "truncated weights");
+    }
+    std::vector<float> W(nw), b(co);
+    std::memcpy(W.data(), p + off, 4 * nw);
+    off += 4 * nw;
+    std::memcpy(b.data(), p + off, 4 * co);
+    off += 4 * co;
+    std::vector<double> Wd(W.begin(), W.end()), bd(b.begin(), b.end());
+    if (has_bn) {
+      std::vector<float> g(co), beta(co), mean(co), var(co);
+      std::memcpy(g.data(), p + off, 4 * co);
+      std::memcpy(beta.data(), p + off + 4 * co, 4 * co);
+      std::memcpy(mean.data(), p + off + 8 * co, 4 * co);
+      std::memcpy(var.data(), p + off + 12 * co, 4 * co);
+      float eps;
+      std::memcpy(&eps, p + off + 16 * co, 4);
+      off += 16 * co + 4;
+      for (uint32_t o = 0; o < co; ++o) {
+        const double sc = (double)g[o] / std::sqrt((double)var[o] + (double)eps);
+        for (size_t i = 0; i < (size_t)ci * k * k; ++i) Wd[o * ci * k * k + i] *= sc;
+        bd[o] = (bd[o] - (double)mean[o]) * sc + (double)beta[o];
+      }
+    }
+    ConvLayer cl;
+    cl.cout = (int)co;
+    cl.cin = (int)ci;
+    cl.k = (int)k;
+    if (li == nconv - 1) {
+      // head: float32 [3][c_in] for every precision
+      std::vector<float> hw((size_t)co * ci), hb(co);
+      for (size_t i = 0; i < hw.size(); ++i) hw[i] = (float)Wd[i];
+      for (uint32_t o = 0; o < co; ++o) hb[o] = (float)bd[o];
+      cl.cout_pad = (int)co;
+      cl.cin_pad = (int)ci;
+      if ((st = upload(hw.data(), 4 * hw.size(), &cl.w)) != LNR_OK) return free_all(), st;
+      void *bp;
+      if ((st = upload(hb.data(), 4 * hb.size(), &bp)) != LNR_OK) return free_all(), st;
+      cl.bias = static_cast<float *>(bp);
+      u->head = cl;
+      continue;
+    }
+    cl.cout_pad = ((int)co + 31) / 32 * 32;
+    cl.cin_pad = (li == 0) ? u->cin0_pad : (int)ci;
+    const size_t np = (size_t)cl.cout_pad * 9 * cl.cin_pad;
+    std::vector<float> packed(np, 0.f);
+    for (int o = 0; o < (int)co; ++o)
+      for (int i = 0; i < (int)ci; ++i)
+        for (int t = 0; t < 9; ++t)
+          packed[((size_t)o * 9 + t) * cl.cin_pad + i] = (float)Wd[((size_t)o * ci + i) * 9 + t];
+    std::vector<float> bias(cl.cout_pad, 0.f);
+    for (int o = 0; o < (int)co; ++o) bias[o] = (float)bd[o];
+    void *bp;
+    if ((st = upload(bias.data(), 4 * bias.size(), &bp)) != LNR_OK) return free_all(), st;
+    cl.bias = static_cast<float *>(bp);
+    if (u->prec == Prec::F32) {
+      if ((st = upload(packed.data(), 4 * np, &cl.w)) != LNR_OK) return free_all(), st;
+    } else {
+      std::vector<uint16_t> hi(np), lo(np);
+      for (size_t i = 0; i < np; ++i) {
+        hi[i] = host_f2bf(packed[i]);
+        lo[i] = host_f2bf(packed[i] - host_bf2f(hi[i]));
+      }
+      if ((st = upload(hi.data(), 2 * np, &cl.w)) != LNR_OK) return free_all(), st;
+      if (u->prec == Prec::BF16X3)
+        if ((st = upload(lo.data(), 2 * np, &cl.w_lo)) != LNR_OK) return free_all(), st;
+    }
+    u->convs.push_back(cl);
+  }
+  if (off != bytes) {
+    free_all();
+    return fail(ctx, LNR_E_FORMAT, "trailing bytes after the last record");
+  }
+  *out = u.release();
+  return LNR_OK;
+}
+
+void lnr_unet_destroy(lnr_unet *u) {
+  if (!u) return;
+  (void)hipSetDevice(u->ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto &a : u->allocs) dfree(u->ctx, a.first, a.second);
+  delete u;
+}
+
+lnr_status lnr_reconstruct(lnr_context *ctx, const lnr_unet *u, const lnr_image *in, float *rgb_out,
+                           void *hip_stream) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!u || !in || !in->depth || !in->rgba || !rgb_out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
+  const int H = in->height, W = in->width, L = u->L;
+  if (H < 1 || W < 1 || H > 16384 || W > 16384) return fail(ctx, LNR_E_INVALID_ARG, "bad image size");
+  if (H % (1 << (L - 1)) || W % (1 << (L - 1)))
+    return fail(ctx, LNR_E_INVALID_ARG, "H and W must be divisible by 2^(levels-1)");
+  if (!aligned(in->depth, 4) || !aligned(in->rgba, 4) || !aligned(rgb_out, 4))
+    return fail(ctx, LNR_E_INVALID_ARG, "misaligned buffers");
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  const size_t es = (u->prec == Prec::BF16) ? 2 : 4;
+  // activation buffers: x0, and per level t, s, p (pooled input), d
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  size_t off = 0;
+  const size_t x0_off = off;
+  off += al((size_t)H * W * u->cin0_pad * es);
+  size_t t_off[6], s_off[6], p_off[6], d_off[6];
+  for (int l = 0; l < L; ++l) {
+    const size_t px = (size_t)(H >> l) * (W >> l);
+    t_off[l] = off;
+    off += al(px * u->widths[l] * es);
+    s_off[l] = off;
+    off += al(px * u->widths[l] * es);
+    d_off[l] = off;
+    off += al(px * u->widths[l] * es);
+    p_off[l] = off;
+    off += (l > 0) ? al(px * u->widths[l - 1] * es) : 0;
+  }
+  if ((st = ensure(ctx, ctx->act, off)) != LNR_OK) return st;
+  char *base = static_cast<char *>(ctx->act.p);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  LNR_LAUNCH(ctx, "pack", s, launch_pack_input(in->depth, reinterpret_cast<const uint32_t *>(in->rgba), H, W, u->cin0_pad, u->prec,
+                                 base + x0_off, s));
+  int li = 0;
+  for (int l = 0; l < L; ++l) {
+    const int Hl = H >> l, Wl = W >> l;
+    ConvCall a{};
+    a.in0 = (l == 0) ? (const void *)(base + x0_off) : (const void *)(base + p_off[l]);
+    a.C0 = (l == 0) ? u->cin0_pad : u->widths[l - 1];
+    a.in1 = nullptr;
+    a.C1 = 0;
+    a.H = Hl;
+    a.W = Wl;
+    a.layer = &u->convs[li++];
+    a.out = base + t_off[l];
+    a.out_pool = nullptr;
+    LNR_LAUNCH(ctx, kConvNames[0][l][0], s, launch_conv3x3(a, u->prec, s));
+    ConvCall b{};
+    b.in0 = base + t_off[l];
+    b.C0 = u->widths[l];
+    b.H = Hl;
+    b.W = Wl;
+    b.layer = &u->convs[li++];
+    b.out = base + s_off[l];
+    b.out_pool = (l < L - 1) ? (void *)(base + p_off[l + 1]) : nullptr;
+    LNR_LAUNCH(ctx, kConvNames[0][l][1], s, launch_conv3x3(b, u->prec, s));
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const int Hl = H >> l, Wl = W >> l;
+    ConvCall a{};
+    a.in0 = base + s_off[l];
+    a.C0 = u->widths[l];
+    a.in1 = (l == L - 2) ? (const void *)(base + s_off[L - 1]) : (const void *)(base + d_off[l + 1]);
+    a.C1 = u->widths[l + 1];
+    a.H = Hl;
+    a.W = Wl;
+    a.layer = &u->convs[li++];
+    a.out = base + t_off[l];
+    LNR_LAUNCH(ctx, kConvNames[1][l][0], s, launch_conv3x3(a, u->prec, s));
+    ConvCall b{};
+    b.in0 = base + t_off[l];
+    b.C0 = u->widths[l];
+    b.H = Hl;
+    b.W = Wl;
+    b.layer = &u->convs[li++];
+    b.out = base + d_off[l];
+    LNR_LAUNCH(ctx, kConvNames[1][l][1], s, launch_conv3x3(b, u->prec, s));
+  }
+  const void *last = (L == 1) ? (const void *)(base + s_off[0]) : (const void *)(base + d_off[0]);
+  LNR_LAUNCH(ctx, "head", s, launch_head(last, u->widths[0], H, W, u->head, u->prec, rgb_out, s));
+  ctx->last_stream = s;
+  return LNR_OK;
+}
+
+lnr_status lnr_sync(lnr_context *ctx, void *hip_stream) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  LNR_HIP(ctx, hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+  LNR_HIP(ctx, hipGetLastError());
+  return LNR_OK;
+}
+
+lnr_status lnr_profile_enable(lnr_context *ctx, int enable) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  ctx->profiling = enable != 0;
+  return LNR_OK;
+}
+
+lnr_status lnr_profile_read(lnr_context *ctx, lnr_kernel_time *out, int32_t max, int32_t *count) {
+  if (!ctx || !count || (max > 0 && !out)) return ctx ? fail(ctx, LNR_E_INVALID_ARG, "bad arguments") : LNR_E_INVALID_ARG;
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  *count = (int32_t)ctx->recs.size();
+  hipError_t err = hipSuccess;
+  if (!ctx->recs.empty()) err = hipEventSynchronize(ctx->recs.back().b);
+  for (size_t i = 0; i < ctx->recs.size(); ++i) {
+    auto &r = ctx->recs[i];
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, r.a, r.b);
+    if ((int32_t)i < max) out[i] = lnr_kernel_time{r.name, ms};
+    ctx->event_pool.push_back(r.a);
+    ctx->event_pool.push_back(r.b);
+  }
+  ctx->recs.clear();
+  if (err != hipSuccess) return hip_fail(ctx, err, "hipEventElapsedTime");
+  return LNR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal declarations shared by the host runtime (api.cpp) and the HIP
+// kernel files of liblnr.  Not part of the public ABI (see include/lnr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lnr.h"
+
+namespace lnr {
+
+// ----------------------------------------------------------------------------
+// geometry of a partitioned cloud (device-resident)
+// ----------------------------------------------------------------------------
+struct CloudDev {
+  uint32_t n = 0;
+  uint32_t n_cells = 0;
+  int32_t dims[3] = {0, 0, 0};
+  float origin[3] = {0, 0, 0};
+  float cell_size = 0;
+  uint32_t max_chunks = 0;    // sum over cells of ceil(count / kSplatChunk)
+  float *x = nullptr, *y = nullptr, *z = nullptr;  // sorted SoA coordinates
+  uint32_t *rgbx = nullptr;   // sorted colours, bytes r, g, b, 0
+  uint32_t *perm = nullptr;   // sorted position -> input index
+  uint32_t *cell_start = nullptr;  // [n_cells + 1]
+  float *aabb = nullptr;      // [n_cells][6] = lo xyz, hi xyz
+};
+
+constexpr uint32_t kSplatChunk = 4096;   // points per splat work item
+constexpr int kSplatThreads = 256;
+
+// frustum-cull parameters, formed on the host in double precision
+struct CullParams {
+  double hs[6][4];     // half-spaces h(X) = c0 x + c1 y + c2 z + c3 >= 0
+  double absP[3][4];   // |P| for the rounding slack
+  double wh1;          // W + H + 1
+  int no_cull;
+};
+
+struct SplatCam {
+  float P[12];
+  float Wf, Hf, z_near, z_far;
+  uint32_t W;
+};
+
+// counters written by the render kernels: [0] chunks, [1] visible cells, [2..3] processed points (u64)
+constexpr int kCounterWords = 4;
+
+// ----------------------------------------------------------------------------
+// kernel launchers (each returns hipGetLastError() of its launches)
+// ----------------------------------------------------------------------------
+// grid.hip
+hipError_t launch_bbox(const float *xyz, uint32_t n, float *partial /* [nb][7] */, uint32_t nb, hipStream_t s);
+uint32_t bbox_blocks(uint32_t n);
+hipError_t launch_cell_ids(const float *xyz, uint32_t n, const double lo[3], double s, const int32_t dims[3],
+                           uint32_t *cell, hipStream_t st);
+hipError_t launch_cell_bounds(const uint32_t *sorted_cell, uint32_t n, uint32_t n_cells, uint32_t *cell_start,
+                              hipStream_t s);
+hipError_t launch_iota(uint32_t *v, uint32_t n, hipStream_t s);
+// stable LSD radix sort of (key, val) pairs by the low `bits` bits of key; uses two ping-pong buffers.
+// On return the sorted data are in (*keys, *vals); tmp buffers are swapped in as needed.
+size_t radix_sort_scratch_bytes(uint32_t n);
+hipError_t radix_sort_pairs(uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt, uint32_t n,
+                            int bits, void *scratch, hipStream_t s);
+size_t scan_scratch_bytes(uint32_t n);
+hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint32_t n, void *scratch, hipStream_t s);
+hipError_t launch_gather_points(const float *xyz, const uint8_t *rgb, const uint32_t *perm, uint32_t n, float *x,
+                                float *y, float *z, uint32_t *rgbx, hipStream_t s);
+hipError_t launch_cell_aabb(const float *x, const float *y, const float *z, const uint32_t *cell_start,
+                            uint32_t n_cells, float *aabb, hipStream_t s);
+hipError_t launch_chunk_count(const uint32_t *cell_start, uint32_t n_cells, uint32_t *total, hipStream_t s);
+
+// render.hip
+hipError_t launch_clear(uint64_t *key, uint32_t npix, uint32_t *counters, hipStream_t s);
+hipError_t launch_cull(const CloudDev &c, const CullParams &prm, uint8_t *flags, uint2 *chunks, uint32_t *counters,
+                       hipStream_t s);
+hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, const uint32_t *counters, const SplatCam &cam,
+                        uint64_t *key, hipStream_t s);
+hipError_t launch_resolve(const uint64_t *key, const uint32_t *rgbx, float *depth, uint32_t *rgba, uint32_t npix,
+                          hipStream_t s);
+
+// filter.hip
+hipError_t launch_pyramid(const float *depth, const uint32_t *rgba, int H, int W, int n, float *const *levels,
+                          hipStream_t s);
+hipError_t launch_upsample(int k, int n, const float *const *D, float *const *U, const int *Hs, const int *Ws,
+                           float *depth, uint32_t *rgba, float fs, float one_plus_fs, hipStream_t s);
+
+// unet.hip
+enum class Prec { F32 = 0, BF16 = 1, BF16X3 = 2 };
+
+struct ConvLayer {
+  int cout = 0, cin = 0, k = 3;  // logical sizes
+  int cout_pad = 0;              // multiple of 32 (MFMA block rows)
+  int cin_pad = 0;               // multiple of 8 (fp32) / 16 (bf16)
+  void *w = nullptr;             // packed weights [cout_pad][k*k][cin_pad] (f32 or bf16 hi)
+  void *w_lo = nullptr;          // bf16 low parts (BF16X3)
+  float *bias = nullptr;         // [cout_pad]
+};
+
+struct ConvCall {
+  const void *in0;   // NHWC, C0 channels, H x W
+  const void *in1;   // NHWC, C1 channels, (H/2) x (W/2), read nearest-upsampled (decoder), or null
+  int C0, C1;
+  int H, W;
+  const ConvLayer *layer;
+  void *out;         // NHWC, layer->cout channels
+  void *out_pool;    // NHWC, (H/2) x (W/2), 2x2 max of out, or null
+};
+
+hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, int W, int cpad, Prec p, void *x,
+                             hipStream_t s);
+hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s);
+hipError_t launch_head(const void *x, int C, int H, int W, const ConvLayer &head, Prec p, float *out, hipStream_t s);
+
+}  // namespace lnr

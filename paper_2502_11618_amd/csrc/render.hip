@@ -1,0 +1,170 @@
+// Per-frame projection: grid-cell frustum culling, 1x1-pixel splat into a
+// 64-bit z-buffer, and RGBDA resolve.
+//
+// Method, "Point Cloud Projection" and Fig. 1: the space-partitioned cloud is
+// culled against the view frustum per grid cell; every surviving point is
+// rasterised to a single pixel; a z-buffer resolves collisions; the result is
+// RGB, depth D and a binary fill mask A.
+//
+// Exactness: the per-point arithmetic is float32 in a fixed order with no
+// fused multiply-add (the library is built with -ffp-contract=off) and a
+// correctly rounded division; the z-buffer keeps min(depth bits << 32 | index),
+// which is order independent, so the image does not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include "lnr_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace lnr {
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ __launch_bounds__(kThreads) void clear_kernel(uint64_t *__restrict__ key, uint32_t npix,
+                                                         uint32_t *__restrict__ counters) {
+  const uint32_t stride = gridDim.x * kThreads;
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < npix; i += stride) key[i] = ~0ull;
+  if (blockIdx.x == 0 && threadIdx.x < kCounterWords) counters[threadIdx.x] = 0;
+}
+
+// One lane per cell.  A non-empty cell is visible unless some half-space's
+// maximum over the cell's box is below -slack (all in double, in the order
+// below).  Visible cells are compacted into splat work items of at most
+// kSplatChunk points with a wave-wide prefix sum and one atomic per wave.
+__global__ __launch_bounds__(kThreads) void cull_kernel(const float *__restrict__ aabb,
+                                                        const uint32_t *__restrict__ cell_start, uint32_t n_cells,
+                                                        CullParams prm, uint8_t *__restrict__ flags,
+                                                        uint2 *__restrict__ chunks, uint32_t *__restrict__ counters) {
+  const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  uint32_t start = 0, cnt = 0;
+  bool vis = false;
+  if (c < n_cells) {
+    start = cell_start[c];
+    cnt = cell_start[c + 1] - start;
+    if (cnt > 0) {
+      if (prm.no_cull) {
+        vis = true;
+      } else {
+        const double lo0 = aabb[6ull * c + 0], lo1 = aabb[6ull * c + 1], lo2 = aabb[6ull * c + 2];
+        const double hi0 = aabb[6ull * c + 3], hi1 = aabb[6ull * c + 4], hi2 = aabb[6ull * c + 5];
+        const double mx0 = fmax(fabs(lo0), fabs(hi0));
+        const double mx1 = fmax(fabs(lo1), fabs(hi1));
+        const double mx2 = fmax(fabs(lo2), fabs(hi2));
+        double S[3];
+        for (int r = 0; r < 3; ++r)
+          S[r] = ((prm.absP[r][0] * mx0 + prm.absP[r][1] * mx1) + prm.absP[r][2] * mx2) + prm.absP[r][3];
+        const double slack = 0x1p-20 * ((S[0] + S[1]) + prm.wh1 * S[2]);
+        vis = true;
+        for (int h = 0; h < 6; ++h) {
+          const double *k = prm.hs[h];
+          const double m =
+              ((fmax(k[0] * lo0, k[0] * hi0) + fmax(k[1] * lo1, k[1] * hi1)) + fmax(k[2] * lo2, k[2] * hi2)) + k[3];
+          if (m < -slack) vis = false;
+        }
+      }
+    }
+    flags[c] = vis ? 1 : 0;
+  }
+  // wave-wide compaction of the visible cells' work items
+  const uint32_t nch = vis ? (cnt + kSplatChunk - 1) / kSplatChunk : 0u;
+  uint32_t incl = nch;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  const uint32_t wave_chunks = __shfl(incl, 63, 64);
+  const uint64_t vis_mask = __ballot(vis);
+  uint32_t pts = vis ? cnt : 0u;
+  for (int off = 32; off > 0; off >>= 1) pts += __shfl_xor(pts, off, 64);
+  uint32_t base = 0;
+  if (lane == 0 && wave_chunks) {
+    base = atomicAdd(&counters[0], wave_chunks);
+    atomicAdd(&counters[1], (uint32_t)__popcll(vis_mask));
+    atomicAdd(reinterpret_cast<unsigned long long *>(&counters[2]), (unsigned long long)pts);
+  }
+  base = __shfl(base, 0, 64);
+  uint32_t pos = base + incl - nch;
+  for (uint32_t k = 0; k < nch; ++k) {
+    const uint32_t off = k * kSplatChunk;
+    chunks[pos + k] = make_uint2(start + off, min(kSplatChunk, cnt - off));
+  }
+}
+
+// One block per work item.  Keys only ever decrease, so a plain (possibly
+// stale) read of the pixel's key is an upper bound of its current value and
+// the atomic can be skipped when the new key is not smaller.
+__global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
+                                                         const float *__restrict__ zs, const uint2 *__restrict__ chunks,
+                                                         const uint32_t *__restrict__ counters, SplatCam cam,
+                                                         uint64_t *__restrict__ key) {
+  if (blockIdx.x >= counters[0]) return;
+  const uint2 ch = chunks[blockIdx.x];
+  const float *P = cam.P;
+  for (uint32_t i = threadIdx.x; i < ch.y; i += kThreads) {
+    const uint32_t j = ch.x + i;
+    const float x = xs[j], y = ys[j], z = zs[j];
+    const float a = ((P[0] * x + P[1] * y) + P[2] * z) + P[3];
+    const float b = ((P[4] * x + P[5] * y) + P[6] * z) + P[7];
+    const float w = ((P[8] * x + P[9] * y) + P[10] * z) + P[11];
+    if (!(w >= cam.z_near && w <= cam.z_far)) continue;
+    const float u = a / w;
+    const float v = b / w;
+    if (!(u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf)) continue;
+    const uint32_t px = (uint32_t)u, py = (uint32_t)v;
+    const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | j;
+    uint64_t *dst = key + (size_t)py * cam.W + px;
+    if (k < *dst) atomicMin(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)k);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void resolve_kernel(const uint64_t *__restrict__ key,
+                                                           const uint32_t *__restrict__ rgbx, float *__restrict__ depth,
+                                                           uint32_t *__restrict__ rgba, uint32_t npix) {
+  const uint32_t stride = gridDim.x * kThreads;
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < npix; i += stride) {
+    const uint64_t k = key[i];
+    if (k == ~0ull) {
+      depth[i] = 0.f;
+      rgba[i] = 0u;
+    } else {
+      depth[i] = __uint_as_float((uint32_t)(k >> 32));
+      rgba[i] = (rgbx[(uint32_t)k] & 0x00FFFFFFu) | (1u << 24);
+    }
+  }
+}
+
+inline uint32_t grid_for(uint32_t n) {
+  uint32_t b = (n + kThreads - 1) / kThreads;
+  return b < 1 ? 1 : (b > 8192 ? 8192 : b);
+}
+
+}  // namespace
+
+hipError_t launch_clear(uint64_t *key, uint32_t npix, uint32_t *counters, hipStream_t s) {
+  clear_kernel<<<grid_for(npix), kThreads, 0, s>>>(key, npix, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_cull(const CloudDev &c, const CullParams &prm, uint8_t *flags, uint2 *chunks, uint32_t *counters,
+                       hipStream_t s) {
+  const uint32_t nb = (c.n_cells + kThreads - 1) / kThreads;
+  cull_kernel<<<nb, kThreads, 0, s>>>(c.aabb, c.cell_start, c.n_cells, prm, flags, chunks, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, const uint32_t *counters, const SplatCam &cam,
+                        uint64_t *key, hipStream_t s) {
+  if (c.max_chunks == 0) return hipSuccess;
+  splat_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, counters, cam, key);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve(const uint64_t *key, const uint32_t *rgbx, float *depth, uint32_t *rgba, uint32_t npix,
+                          hipStream_t s) {
+  resolve_kernel<<<grid_for(npix), kThreads, 0, s>>>(key, rgbx, depth, rgba, npix);
+  return hipGetLastError();
+}
+
+}  // namespace lnr

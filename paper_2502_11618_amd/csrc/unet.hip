@@ -1,0 +1,364 @@
+// U-Net forward pass on the gfx950 matrix cores.
+//
+// Fig. 1 and Method, "U-Net Reconstruction": a fully convolutional U-Net maps
+// the depth-filtered RGBDA image to RGB.  Each 3x3 convolution is an implicit
+// GEMM (M = output channels, N = output pixels, K = 9 taps x input channels):
+// a workgroup stages an input tile with a one-pixel halo in LDS and runs the
+// K loop on 32x32 MFMA blocks.  The decoder's nearest-neighbour upsample and
+// channel concatenation are folded into the tile load (channels past the skip
+// tensor are read from the coarser tensor at (y/2, x/2)), and the encoder's
+// 2x2 max-pool is folded into the epilogue of the convolution that feeds it.
+//
+// Arithmetic modes:
+//   F32    float32 activations, v_mfma_f32_32x32x2_f32.
+//   BF16   bfloat16 activations and weights, v_mfma_f32_32x32x16_bf16,
+//          float32 accumulation, round-to-nearest-even to bfloat16 on store.
+//   BF16X3 float32 activations; operands split into bfloat16 hi + lo in LDS,
+//          hi*hi + hi*lo + lo*hi on the bf16 MFMA with float32 accumulation.
+#include <hip/hip_runtime.h>
+
+#include "lnr_internal.h"
+
+namespace lnr {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kTH = 8;    // output tile rows
+constexpr int kTW = 32;   // output tile columns
+constexpr int kLH = kTH + 2, kLW = kTW + 2, kLPix = kLH * kLW;
+
+__device__ inline uint16_t f2bf(float f) {  // round to nearest even (finite inputs)
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+struct ConvArgs {
+  const void *in0;
+  const void *in1;
+  int C0, C1, H, W;
+  const void *w;
+  const void *w_lo;
+  const float *bias;
+  int cout, cin_pad;
+  void *out;
+  void *out_pool;
+};
+
+// LDS layout: per tile pixel, CK channels plus padding that staggers pixels
+// across banks (16-byte lane reads).
+template <int MODE, int CK>
+struct Lds {
+  static constexpr int kStride = (MODE == 0) ? (CK + 4) : (CK + 8);  // elements per pixel
+  using T = typename std::conditional<MODE == 0, float, uint16_t>::type;
+  static constexpr int kArrays = (MODE == 2) ? 2 : 1;
+};
+
+template <int MODE, int BM, int CK>
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
+  using L = Lds<MODE, CK>;
+  using T = typename L::T;
+  constexpr int S = L::kStride;
+  constexpr int MB = BM / 32;
+  __shared__ __attribute__((aligned(16))) T s_in[L::kArrays][kLPix * S];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = lane & 31, h = lane >> 5;
+  const int ty0 = blockIdx.y * kTH, tx0 = blockIdx.x * kTW;
+  const int co0 = blockIdx.z * BM;
+  const int H = a.H, W = a.W;
+  const int Cin = a.C0 + a.C1;
+
+  floatx16 acc[MB][2];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.f;
+
+  // pixel of this lane in each N block (2 rows x 16 columns), tile coordinates
+  const int pr = 2 * wv + (n >> 4);
+  const int pc = n & 15;
+
+  for (int ci = 0; ci < Cin; ci += CK) {
+    // ---- stage the input tile (with halo) for channels [ci, ci + CK) ----
+    const bool from0 = ci < a.C0;
+    const int csrc = from0 ? a.C0 : a.C1;
+    const int coff = from0 ? ci : ci - a.C0;
+    constexpr int VEC = (MODE == 1) ? 8 : 4;  // channels per 16-byte global load
+    constexpr int NV = CK / VEC;
+    for (int e = tid; e < kLPix * NV; e += 256) {
+      const int pix = e / NV, q = e - pix * NV;
+      const int gy = ty0 - 1 + pix / kLW, gx = tx0 - 1 + pix % kLW;
+      const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      size_t gi = 0;
+      if (inside) {
+        gi = from0 ? ((size_t)gy * W + gx) * csrc + coff + q * VEC
+                   : ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * csrc + coff + q * VEC;
+      }
+      const void *src = from0 ? a.in0 : a.in1;
+      if (MODE == 0) {
+        float4 v = inside ? *reinterpret_cast<const float4 *>(static_cast<const float *>(src) + gi)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+        *reinterpret_cast<float4 *>(&s_in[0][pix * S + q * 4]) = v;
+      } else if (MODE == 1) {
+        uint4 v = inside ? *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(src) + gi)
+                         : make_uint4(0u, 0u, 0u, 0u);
+        *reinterpret_cast<uint4 *>(&s_in[0][pix * S + q * 8]) = v;
+      } else {
+        float4 v = inside ? *reinterpret_cast<const float4 *>(static_cast<const float *>(src) + gi)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float f[4] = {v.x, v.y, v.z, v.w};
+        uint16_t hi[4], lo[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          hi[i] = f2bf(f[i]);
+          lo[i] = f2bf(f[i] - bf2f(hi[i]));
+        }
+        *reinterpret_cast<uint2 *>(&s_in[0][pix * S + q * 4]) =
+            make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
+        *reinterpret_cast<uint2 *>(&s_in[MODE == 2 ? 1 : 0][pix * S + q * 4]) =
+            make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+      }
+    }
+    __syncthreads();
+
+    // ---- K loop over the 9 taps and the staged channels ----
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+      int boff[2];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) boff[nb] = ((pr + dy) * kLW + (nb * 16 + pc + dx)) * S;
+      if (MODE == 0) {
+        const float *wp = static_cast<const float *>(a.w);
+#pragma unroll
+        for (int g = 0; g < CK / 8; ++g) {
+          float4 av[MB], bv[2];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+            av[mb] = *reinterpret_cast<const float4 *>(
+                wp + ((size_t)(co0 + mb * 32 + n) * 9 + tap) * a.cin_pad + ci + g * 8 + 4 * h);
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            bv[nb] = *reinterpret_cast<const float4 *>(
+                reinterpret_cast<const float *>(&s_in[0][0]) + boff[nb] + g * 8 + 4 * h);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+              for (int nb = 0; nb < 2; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][i], bv[nb][i], acc[mb][nb], 0, 0, 0);
+        }
+      } else {
+        const uint16_t *wp = static_cast<const uint16_t *>(a.w);
+        const uint16_t *wl = static_cast<const uint16_t *>(a.w_lo);
+#pragma unroll
+        for (int g = 0; g < CK / 16; ++g) {
+          uint4 ah[MB], al[MB], bh[2], bl[2];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+            const size_t wi = ((size_t)(co0 + mb * 32 + n) * 9 + tap) * a.cin_pad + ci + g * 16 + 8 * h;
+            ah[mb] = *reinterpret_cast<const uint4 *>(wp + wi);
+            if (MODE == 2) al[mb] = *reinterpret_cast<const uint4 *>(wl + wi);
+          }
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            bh[nb] = *reinterpret_cast<const uint4 *>(&s_in[0][boff[nb] + g * 16 + 8 * h]);
+            if (MODE == 2) bl[nb] = *reinterpret_cast<const uint4 *>(&s_in[MODE == 2 ? 1 : 0][boff[nb] + g * 16 + 8 * h]);
+          }
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+              if (MODE == 2) {
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(al[mb]), as_bf16x8(bh[nb]),
+                                                                      acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah[mb]), as_bf16x8(bl[nb]),
+                                                                      acc[mb][nb], 0, 0, 0);
+              }
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah[mb]), as_bf16x8(bh[nb]),
+                                                                    acc[mb][nb], 0, 0, 0);
+            }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: bias + ReLU, store NHWC, optional fused 2x2 max-pool ----
+  // accumulator register r = 4j + i holds output channel 8j + 4h + i of the block
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int gy = ty0 + pr, gx = tx0 + nb * 16 + pc;
+      const bool inside = gy < H && gx < W;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = co0 + mb * 32 + 8 * j + 4 * h;
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[mb][nb][4 * j + i] + a.bias[c + i], 0.f);
+        const bool store = inside && c < a.cout;
+        if (MODE == 1) {
+          uint16_t b16[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) b16[i] = f2bf(v[i]);
+          if (store)
+            *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(a.out) + ((size_t)gy * W + gx) * a.cout + c) =
+                make_uint2(b16[0] | ((uint32_t)b16[1] << 16), b16[2] | ((uint32_t)b16[3] << 16));
+        } else {
+          if (store)
+            *reinterpret_cast<float4 *>(static_cast<float *>(a.out) + ((size_t)gy * W + gx) * a.cout + c) =
+                make_float4(v[0], v[1], v[2], v[3]);
+        }
+        if (a.out_pool) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            v[i] = fmaxf(v[i], __shfl_xor(v[i], 1, 64));
+            v[i] = fmaxf(v[i], __shfl_xor(v[i], 16, 64));
+          }
+          if (store && (pc & 1) == 0 && (pr & 1) == 0) {
+            const size_t pi = ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * a.cout + c;
+            if (MODE == 1) {
+              uint16_t b16[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) b16[i] = f2bf(v[i]);
+              *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(a.out_pool) + pi) =
+                  make_uint2(b16[0] | ((uint32_t)b16[1] << 16), b16[2] | ((uint32_t)b16[3] << 16));
+            } else {
+              *reinterpret_cast<float4 *>(static_cast<float *>(a.out_pool) + pi) = make_float4(v[0], v[1], v[2], v[3]);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// RGBDA -> network input x = (r/255, g/255, b/255, A ? D/16 : 0, A, 0...), cpad channels
+template <int MODE>
+__global__ __launch_bounds__(256) void pack_kernel(const float *__restrict__ depth, const uint32_t *__restrict__ rgba,
+                                                   int npix, int cpad, void *__restrict__ x) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const uint32_t q = rgba[p];
+  const bool A = (q >> 24) != 0;
+  float v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = 0.f;
+  v[0] = (float)(q & 255u) / 255.0f;
+  v[1] = (float)((q >> 8) & 255u) / 255.0f;
+  v[2] = (float)((q >> 16) & 255u) / 255.0f;
+  v[3] = A ? depth[p] * 0.0625f : 0.f;
+  v[4] = A ? 1.f : 0.f;
+  if (MODE == 1) {
+    uint16_t *o = static_cast<uint16_t *>(x) + (size_t)p * cpad;
+    for (int i = 0; i < cpad; i += 2) *reinterpret_cast<uint32_t *>(o + i) = f2bf(v[i]) | ((uint32_t)f2bf(v[i + 1]) << 16);
+  } else {
+    float *o = static_cast<float *>(x) + (size_t)p * cpad;
+    for (int i = 0; i < cpad; i += 4) *reinterpret_cast<float4 *>(o + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+  }
+}
+
+// 1x1 head, float32 weights [3][C], one thread per pixel, planar float32 output
+template <int MODE>
+__global__ __launch_bounds__(256) void head_kernel(const void *__restrict__ x, int C, int npix,
+                                                   const float *__restrict__ w, const float *__restrict__ b,
+                                                   float *__restrict__ out) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  float y0 = b[0], y1 = b[1], y2 = b[2];
+  for (int c = 0; c < C; c += 4) {
+    float v[4];
+    if (MODE == 1) {
+      const uint2 q = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(x) + (size_t)p * C + c);
+      v[0] = __uint_as_float(q.x << 16);
+      v[1] = __uint_as_float(q.x & 0xFFFF0000u);
+      v[2] = __uint_as_float(q.y << 16);
+      v[3] = __uint_as_float(q.y & 0xFFFF0000u);
+    } else {
+      const float4 q = *reinterpret_cast<const float4 *>(static_cast<const float *>(x) + (size_t)p * C + c);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      y0 = fmaf(w[c + i], v[i], y0);
+      y1 = fmaf(w[C + c + i], v[i], y1);
+      y2 = fmaf(w[2 * C + c + i], v[i], y2);
+    }
+  }
+  out[p] = y0;
+  out[(size_t)npix + p] = y1;
+  out[2 * (size_t)npix + p] = y2;
+}
+
+template <int MODE, int BM, int CK>
+hipError_t conv_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
+  dim3 grid((a.W + kTW - 1) / kTW, (a.H + kTH - 1) / kTH, cout_pad / BM);
+  conv3x3_kernel<MODE, BM, CK><<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int MODE, int BM>
+hipError_t conv_dispatch_ck(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
+  if (ck == 32) return conv_launch<MODE, BM, 32>(a, cout_pad, s);
+  if (ck == 16) return conv_launch<MODE, BM, 16>(a, cout_pad, s);
+  if (MODE == 0 && ck == 8) return conv_launch<0, BM, 8>(a, cout_pad, s);
+  return hipErrorInvalidValue;
+}
+
+template <int MODE>
+hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
+  if (cout_pad % 64 == 0) return conv_dispatch_ck<MODE, 64>(a, ck, cout_pad, s);
+  return conv_dispatch_ck<MODE, 32>(a, ck, cout_pad, s);
+}
+
+}  // namespace
+
+hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, int W, int cpad, Prec p, void *x,
+                             hipStream_t s) {
+  const int npix = H * W;
+  const int nb = (npix + 255) / 256;
+  if (p == Prec::BF16)
+    pack_kernel<1><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
+  else
+    pack_kernel<0><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s) {
+  const ConvLayer &L = *c.layer;
+  ConvArgs a{c.in0, c.in1, c.C0, c.C1, c.H, c.W, L.w, L.w_lo, L.bias, L.cout, L.cin_pad, c.out, c.out_pool};
+  const int step = (p == Prec::F32) ? 8 : 16;
+  int ck = 32;
+  while (ck > step && ((c.C0 % ck) != 0 || (c.C1 % ck) != 0)) ck >>= 1;
+  if ((c.C0 % ck) != 0 || (c.C1 % ck) != 0 || (c.C0 + c.C1) != L.cin_pad) return hipErrorInvalidValue;
+  switch (p) {
+    case Prec::F32: return conv_dispatch<0>(a, ck, L.cout_pad, s);
+    case Prec::BF16: return conv_dispatch<1>(a, ck, L.cout_pad, s);
+    case Prec::BF16X3: return conv_dispatch<2>(a, ck, L.cout_pad, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_head(const void *x, int C, int H, int W, const ConvLayer &head, Prec p, float *out, hipStream_t s) {
+  const int npix = H * W;
+  const int nb = (npix + 255) / 256;
+  const float *w = static_cast<const float *>(head.w);
+  if (p == Prec::BF16)
+    head_kernel<1><<<nb, 256, 0, s>>>(x, C, npix, w, head.bias, out);
+  else
+    head_kernel<0><<<nb, 256, 0, s>>>(x, C, npix, w, head.bias, out);
+  return hipGetLastError();
+}
+
+}  // namespace lnr

@@ -1,0 +1,142 @@
+"""GPU parity of the partition, culling, splat and resolve against the oracle
+(bit-exact), through the C ABI."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import grid as G
+from oracle import render as R
+from tests.gpu_util import assert_images_equal, image_to_host, render_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_partition_matches_oracle(lnr, room_cloud, room_grid):
+    info = lnr.lnr_cloud_info(room_cloud)
+    assert info["dims"] == room_grid.dims
+    assert np.array_equal(info["origin"], room_grid.lo)
+    assert np.array_equal(lnr.lnr_cloud_permutation(room_cloud), room_grid.perm.astype(np.uint32))
+    assert np.array_equal(lnr.lnr_cloud_cell_start(room_cloud), room_grid.cell_start.astype(np.uint32))
+
+
+@pytest.mark.parametrize("seed,n,s", [(0, 1, 0.5), (1, 7, 0.01), (2, 100_000, 0.5), (3, 300_000, 2.0),
+                                      (4, 50_000, 0.1)])
+def test_partition_random_clouds(lnr, ctx, seed, n, s):
+    """Stable order with duplicated points, a grid of millions of mostly empty
+    cells (0.1 m cells over a Gaussian cloud of radius ~8 m) and a single point."""
+    rng = np.random.default_rng(seed)
+    xyz = (rng.standard_normal((n, 3)) * 2).astype(np.float32)
+    if n > 20:
+        xyz[n // 3:n // 3 + 10] = xyz[:10]
+    rgb = rng.integers(0, 256, (n, 3), dtype=np.uint8)
+    g = G.partition(xyz, rgb, s)
+    cloud = lnr.lnr_cloud_load(ctx, xyz, rgb, s)
+    assert lnr.lnr_cloud_info(cloud)["dims"] == g.dims
+    assert np.array_equal(lnr.lnr_cloud_permutation(cloud), g.perm.astype(np.uint32))
+    assert np.array_equal(lnr.lnr_cloud_cell_start(cloud), g.cell_start.astype(np.uint32))
+
+
+def test_cloud_load_rejects_bad_input(lnr, ctx):
+    rng = np.random.default_rng(0)
+    xyz = (rng.standard_normal((1000, 3)) * 2).astype(np.float32)
+    rgb = np.zeros((1000, 3), np.uint8)
+    for bad_s in (0.003, 0.0, -1.0, float("nan"), float("inf")):  # 0.003 m: more than 2^31 cells
+        with pytest.raises(lnr.LnrError) as e:
+            lnr.lnr_cloud_load(ctx, xyz, rgb, bad_s)
+        assert e.value.status == lnr.LNR_E_INVALID_ARG
+    xyz[5, 1] = np.nan
+    with pytest.raises(lnr.LnrError) as e:
+        lnr.lnr_cloud_load(ctx, xyz, rgb, 0.5)
+    assert e.value.status == lnr.LNR_E_INVALID_ARG
+
+
+def test_budget_is_enforced(lnr, room_scene):
+    small = lnr.lnr_context_create(0, 1 << 20)
+    with pytest.raises(lnr.LnrError) as e:
+        lnr.lnr_cloud_load(small, room_scene.xyz, room_scene.rgb, 0.5)
+    assert e.value.status == lnr.LNR_E_BUDGET
+    assert lnr.lnr_allocated_bytes(small) == 0
+
+
+@pytest.mark.parametrize("i", range(16))
+def test_render_room_bit_exact(lnr, ctx, room_cloud, room_grid, room_cams, i):
+    cam = room_cams[i]
+    img = render_gpu(lnr, ctx, room_cloud, cam)
+    vis_gpu, proc_gpu, flags = lnr.lnr_render_stats(ctx, room_grid.n_cells)
+    key, depth, rgba = R.render(room_grid, cam)
+    assert_images_equal(image_to_host(img), (key, depth, rgba), f"frame {i}")
+    vis = G.cull(room_grid, cam.P, cam.width, cam.height, cam.z_near, cam.z_far)
+    assert np.array_equal(flags, vis)
+    assert vis_gpu == int(vis.sum())
+    assert proc_gpu == R.processed_points(room_grid, vis)
+
+
+def test_culled_render_equals_unculled(lnr, ctx, room_cloud, room_cams):
+    for cam in room_cams[:6]:
+        a = image_to_host(render_gpu(lnr, ctx, room_cloud, cam))
+        b = image_to_host(render_gpu(lnr, ctx, room_cloud, cam, flags=lnr.LNR_RENDER_NO_CULL))
+        assert_images_equal(a, b, "cull vs no cull")
+        _, proc_all, _ = lnr.lnr_render_stats(ctx)
+        assert proc_all == 200_000
+
+
+def test_render_grazing_cameras(lnr, ctx, room_cloud, room_grid):
+    """Cameras inside the cloud with near planes and image borders cutting
+    through it, narrow and wide fields of view, odd image sizes."""
+    rng = np.random.default_rng(11)
+    xyz = room_grid
+    for t in range(24):
+        j, k = rng.integers(0, len(room_grid.xs), 2)
+        eye = np.array([room_grid.xs[j], room_grid.ys[j], room_grid.zs[j]], np.float64) + rng.normal(0, 0.2, 3)
+        tgt = np.array([room_grid.xs[k], room_grid.ys[k], room_grid.zs[k]], np.float64)
+        if np.linalg.norm(tgt - eye) < 0.3:
+            continue
+        W, H = int(rng.integers(1, 200)), int(rng.integers(1, 200))
+        cam = synth.look_at(eye, tgt, W, H, float(rng.uniform(10, 150)), float(rng.choice([0.1, 1.0, 3.0])),
+                            float(rng.choice([4.0, 1000.0])))
+        img = render_gpu(lnr, ctx, room_cloud, cam)
+        assert_images_equal(image_to_host(img), R.render(room_grid, cam), f"grazing {t}")
+
+
+def test_render_empty_view_and_tiny_image(lnr, ctx, room_cloud, room_grid):
+    cam = synth.look_at([-5, 4, 1.5], [-10, 4, 1.5], 64, 48, 70.0)  # outside, looking away
+    img = render_gpu(lnr, ctx, room_cloud, cam)
+    k, d, r = image_to_host(img)
+    assert np.all(k == np.uint64(lnr.EMPTY_KEY)) and not d.any() and not r.any()
+    vis, proc, _ = lnr.lnr_render_stats(ctx)
+    assert vis == 0 and proc == 0
+    cam = synth.look_at([5, 4, 1.5], [9, 4, 1.5], 1, 1, 60.0)
+    assert_images_equal(image_to_host(render_gpu(lnr, ctx, room_cloud, cam)), R.render(room_grid, cam), "1x1")
+
+
+def test_render_ties_and_duplicates(lnr, ctx):
+    """Many points at the same depth in one pixel and exact duplicates: the
+    lowest sorted index wins, as in the oracle."""
+    rng = np.random.default_rng(3)
+    base = np.float32([[2.0, 0.01, 0.01], [2.0, 0.02, 0.01], [2.0, 0.01, 0.02]])
+    xyz = np.concatenate([np.repeat(base, 200, axis=0), rng.uniform(-1, 3, (5000, 3)).astype(np.float32)])
+    rgb = rng.integers(0, 256, xyz.shape, dtype=np.uint8)
+    g = G.partition(xyz, rgb, 0.25)
+    cloud = lnr.lnr_cloud_load(ctx, xyz, rgb, 0.25)
+    cam = synth.look_at([0, 0, 0], [1, 0, 0], 16, 16, 90.0)
+    assert_images_equal(image_to_host(render_gpu(lnr, ctx, cloud, cam)), R.render(g, cam), "ties")
+
+
+def test_render_large_image(lnr, ctx, room_cloud, room_grid):
+    cam = synth.look_at([5, 4, 1.5], [9, 2, 1.2], 4096, 3072, 100.0)
+    assert_images_equal(image_to_host(render_gpu(lnr, ctx, room_cloud, cam)), R.render(room_grid, cam), "4k")
+
+
+def test_render_rejects_bad_arguments(lnr, ctx, room_cloud, room_cams):
+    import torch
+    cam = room_cams[0]
+    img = lnr.Image(cam.height, cam.width + 1)
+    with pytest.raises(lnr.LnrError) as e:
+        lnr.lnr_render(ctx, room_cloud, cam, img)
+    assert e.value.status == lnr.LNR_E_INVALID_ARG
+    c = lnr.camera_struct(cam)
+    c.z_near = 0.0
+    with pytest.raises(lnr.LnrError):
+        lnr.lnr_render(ctx, room_cloud, c, lnr.Image(cam.height, cam.width))
+    torch.cuda.synchronize()

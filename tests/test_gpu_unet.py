@@ -1,0 +1,108 @@
+"""GPU U-Net against the float64 oracle: max-abs error bounds per precision.
+
+Bounds: float32 1e-4; the split-bfloat16 mode (hi*hi + hi*lo + lo*hi) 2e-2;
+plain bfloat16 activations + weights 8e-2 (on these He-initialised networks
+one bfloat16 rounding per layer already gives about 1e-2 per layer, so
+plain bfloat16 does not reach 2e-2; the split mode is the bfloat16 path that
+meets it)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import depth_filter as F
+from oracle import metrics as M
+from oracle import render as R
+from oracle import unet as U
+from tests.gpu_util import image_from_host, render_gpu
+
+pytestmark = pytest.mark.gpu
+
+BOUND = {0: 1e-4, 1: 8e-2, 2: 2e-2}
+
+
+def _run(lnr, ctx, net, depth, rgba):
+    import torch
+    img = image_from_host(lnr, depth, rgba)
+    out = torch.empty((3,) + depth.shape, dtype=torch.float32, device="cuda")
+    lnr.lnr_reconstruct(ctx, net, img, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def _random_rgbda(rng, H, W):
+    filled = rng.random((H, W)) < 0.6
+    depth = np.where(filled, rng.uniform(0.2, 40, (H, W)), 0).astype(np.float32)
+    rgba = rng.integers(0, 256, (H, W, 4)).astype(np.uint8)
+    rgba[..., 3] = filled
+    rgba[~filled] = 0
+    return depth, rgba
+
+
+@pytest.mark.parametrize("prec", [0, 2, 1])
+@pytest.mark.parametrize("widths,H,W,bias", [
+    ((16,), 8, 40, "uniform"),
+    ((16, 32), 34, 70, "uniform"),
+    ((16, 32, 64), 64, 64, "zero"),
+    ((32, 64, 128, 256), 72, 112, "uniform"),
+    ((16, 32, 48, 64, 80), 48, 80, "uniform"),
+])
+def test_unet_random_images(lnr, ctx, prec, widths, H, W, bias):
+    blob = synth.make_unet_blob(widths, seed=len(widths), bias=bias)
+    depth, rgba = _random_rgbda(np.random.default_rng(H + W), H, W)
+    ref = U.forward(U.parse_blob(blob), depth, rgba)
+    net = lnr.lnr_unet_load(ctx, blob, prec)
+    got = _run(lnr, ctx, net, depth, rgba)
+    err = M.max_abs(got, ref)
+    assert err <= BOUND[prec], f"prec {prec}: max-abs {err}"
+
+
+def test_unet_batchnorm_folding(lnr, ctx):
+    blob = synth.make_unet_blob((16, 32), seed=9, bias="uniform", batchnorm=True)
+    depth, rgba = _random_rgbda(np.random.default_rng(1), 32, 32)
+    ref = U.forward(U.parse_blob(blob), depth, rgba)
+    got = _run(lnr, ctx, lnr.lnr_unet_load(ctx, blob, lnr.LNR_FP32), depth, rgba)
+    assert M.max_abs(got, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("prec", [0, 2, 1])
+def test_room_pipeline(lnr, ctx, room_cloud, room_grid, room_cams, prec):
+    """Render -> filter -> reconstruct on all 16 room frames (256x256, n = 4,
+    fs = 0.5, widths 16/32/64) against the oracle's float64 network applied to
+    the oracle's filtered image."""
+    import torch
+    blob = synth.make_unet_blob((16, 32, 64), seed=0)
+    onet = U.parse_blob(blob)
+    net = lnr.lnr_unet_load(ctx, blob, prec)
+    worst = 0.0
+    for cam in room_cams:
+        img = render_gpu(lnr, ctx, room_cloud, cam)
+        lnr.lnr_depth_filter(ctx, img, 4, 0.5)
+        out = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device="cuda")
+        lnr.lnr_reconstruct(ctx, net, img, out)
+        torch.cuda.synchronize()
+        _, depth, rgba = R.render(room_grid, cam)
+        H, W = cam.height, cam.width
+        fd, fr, _ = F.depth_filter(depth.reshape(H, W), rgba.reshape(H, W, 4), 4, 0.5)
+        ref = U.forward(onet, fd, fr)
+        worst = max(worst, M.max_abs(out.cpu().numpy(), ref))
+    assert worst <= BOUND[prec], f"prec {prec}: worst max-abs {worst}"
+
+
+def test_reconstruct_rejects_indivisible_size(lnr, ctx):
+    blob = synth.make_unet_blob((16, 32, 64), seed=0)
+    net = lnr.lnr_unet_load(ctx, blob, lnr.LNR_FP32)
+    depth, rgba = _random_rgbda(np.random.default_rng(0), 30, 32)
+    with pytest.raises(lnr.LnrError) as e:
+        _run(lnr, ctx, net, depth, rgba)
+    assert e.value.status == lnr.LNR_E_INVALID_ARG
+
+
+def test_unet_load_rejects_malformed_blobs(lnr, ctx):
+    blob = synth.make_unet_blob((16, 32), seed=0)
+    for bad, st in [(b"XXXX" + blob[4:], lnr.LNR_E_FORMAT), (blob[:-4], lnr.LNR_E_FORMAT),
+                    (blob + b"\0\0\0\0", lnr.LNR_E_FORMAT),
+                    (synth.make_unet_blob((24,), seed=0), lnr.LNR_E_UNSUPPORTED)]:
+        with pytest.raises(lnr.LnrError) as e:
+            lnr.lnr_unet_load(ctx, bad, lnr.LNR_FP32)
+        assert e.value.status == st
