@@ -74,6 +74,33 @@ def resolve(key: np.ndarray, rgb_sorted: np.ndarray):
     return depth, rgba
 
 
+def soft_colors(xs, ys, zs, rgb_sorted, P, W: int, H: int, near, far, key: np.ndarray, eps) -> np.ndarray:
+    """Soft z-buffer colours (Method, "Point Cloud Projection": colours of points
+    that arrive at similar depths are averaged, given a small depth threshold).
+
+    Reading: a point joins pixel p's average iff it lands on p and its depth
+    w <= zmin * (1 + eps) in float32, zmin being the depth of p's nearest point
+    (the hard key); the average of each channel is the integer sum over the
+    joined points rounded half up: (2 * sum + count) // (2 * count).
+    Returns rgba uint8 [P, 4] (alpha 1 where filled)."""
+    valid, pix, k = project(xs, ys, zs, P, W, H, near, far)
+    filled = key != EMPTY_KEY
+    zmin = np.zeros(key.shape[0], dtype=np.float32)
+    zmin[filled] = (key[filled] >> np.uint64(32)).astype(np.uint32).view(np.float32)
+    w = (k >> np.uint64(32)).astype(np.uint32).view(np.float32)
+    thr = zmin[pix] * (np.float32(1) + np.float32(eps))
+    join = valid & (w <= thr)
+    sums = np.zeros((key.shape[0], 3), dtype=np.int64)
+    count = np.zeros(key.shape[0], dtype=np.int64)
+    np.add.at(sums, pix[join], rgb_sorted[join].astype(np.int64))
+    np.add.at(count, pix[join], 1)
+    rgba = np.zeros((key.shape[0], 4), dtype=np.uint8)
+    c = count[filled][:, None]
+    rgba[filled, :3] = ((2 * sums[filled] + c) // (2 * c)).astype(np.uint8)
+    rgba[filled, 3] = 1
+    return rgba
+
+
 def render(grid, cam):
     """Full projection of a partitioned cloud for one camera: (key, depth, rgba).
     `cam` carries P (float32[12]), width, height, z_near, z_far."""

@@ -761,6 +761,9 @@ lnr_status lnr_reconstruct(lnr_context *ctx, const lnr_unet *u, const lnr_image 
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   LNR_LAUNCH(ctx, "pack", s, launch_pack_input(in->depth, reinterpret_cast<const uint32_t *>(in->rgba), H, W, u->cin0_pad, u->prec,
                                  base + x0_off, s));
+  // the 1x1 head runs in the epilogue of the last 3x3 convolution when one
+  // workgroup holds all of its output channels
+  const bool fuse_head = u->widths[0] <= 64;
   int li = 0;
   for (int l = 0; l < L; ++l) {
     const int Hl = H >> l, Wl = W >> l;
@@ -783,6 +786,11 @@ lnr_status lnr_reconstruct(lnr_context *ctx, const lnr_unet *u, const lnr_image 
     b.layer = &u->convs[li++];
     b.out = base + s_off[l];
     b.out_pool = (l < L - 1) ? (void *)(base + p_off[l + 1]) : nullptr;
+    if (L == 1 && fuse_head) {
+      b.head_w = static_cast<const float *>(u->head.w);
+      b.head_b = u->head.bias;
+      b.head_out = rgb_out;
+    }
     LNR_LAUNCH(ctx, kConvNames[0][l][1], s, launch_conv3x3(b, u->prec, s));
   }
   for (int l = L - 2; l >= 0; --l) {
@@ -804,10 +812,17 @@ lnr_status lnr_reconstruct(lnr_context *ctx, const lnr_unet *u, const lnr_image 
     b.W = Wl;
     b.layer = &u->convs[li++];
     b.out = base + d_off[l];
+    if (l == 0 && fuse_head) {
+      b.head_w = static_cast<const float *>(u->head.w);
+      b.head_b = u->head.bias;
+      b.head_out = rgb_out;
+    }
     LNR_LAUNCH(ctx, kConvNames[1][l][1], s, launch_conv3x3(b, u->prec, s));
   }
-  const void *last = (L == 1) ? (const void *)(base + s_off[0]) : (const void *)(base + d_off[0]);
-  LNR_LAUNCH(ctx, "head", s, launch_head(last, u->widths[0], H, W, u->head, u->prec, rgb_out, s));
+  if (!fuse_head) {
+    const void *last = (L == 1) ? (const void *)(base + s_off[0]) : (const void *)(base + d_off[0]);
+    LNR_LAUNCH(ctx, "head", s, launch_head(last, u->widths[0], H, W, u->head, u->prec, rgb_out, s));
+  }
   ctx->last_stream = s;
   return LNR_OK;
 }

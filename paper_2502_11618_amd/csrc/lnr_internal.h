@@ -81,6 +81,10 @@ hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, const uint32_t *
                         uint64_t *key, hipStream_t s);
 hipError_t launch_resolve(const uint64_t *key, const uint32_t *rgbx, float *depth, uint32_t *rgba, uint32_t npix,
                           hipStream_t s);
+// soft z-buffer: clear the colour sums, accumulate, resolve (acc = 4 x u32 per pixel)
+hipError_t launch_soft(const CloudDev &c, const uint2 *chunks, const uint32_t *counters, const SplatCam &cam,
+                       const uint64_t *key, float one_plus_eps, uint32_t *acc, float *depth, uint32_t *rgba,
+                       uint32_t npix, hipStream_t s);
 
 // filter.hip
 hipError_t launch_pyramid(const float *depth, const uint32_t *rgba, int H, int W, int n, float *const *levels,
@@ -108,6 +112,11 @@ struct ConvCall {
   const ConvLayer *layer;
   void *out;         // NHWC, layer->cout channels
   void *out_pool;    // NHWC, (H/2) x (W/2), 2x2 max of out, or null
+  // optional fused 1x1 head (c_out <= 64): when head_out is set, the ReLU output
+  // is not stored; head_out[o][y][x] = head_b[o] + sum_c head_w[o][c] * out[c]
+  const float *head_w = nullptr;  // [3][cout]
+  const float *head_b = nullptr;  // [3]
+  float *head_out = nullptr;      // planar float [3][H][W]
 };
 
 hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, int W, int cpad, Prec p, void *x,

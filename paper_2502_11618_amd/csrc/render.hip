@@ -102,6 +102,57 @@ __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict
   if (blockIdx.x >= counters[0]) return;
   const uint2 ch = chunks[blockIdx.x];
   const float *P = cam.P;
+  // kUnroll points per thread are in flight at once: their coordinate loads,
+  // then their z-buffer reads, then their atomics.
+  constexpr int kUnroll = 4;
+  for (uint32_t base = 0; base < ch.y; base += kThreads * kUnroll) {
+    float x[kUnroll], y[kUnroll], z[kUnroll];
+    bool ok[kUnroll];
+#pragma unroll
+    for (int r = 0; r < kUnroll; ++r) {
+      const uint32_t i = base + r * kThreads + threadIdx.x;
+      ok[r] = i < ch.y;
+      const uint32_t j = ch.x + (ok[r] ? i : 0u);
+      x[r] = xs[j];
+      y[r] = ys[j];
+      z[r] = zs[j];
+    }
+    uint64_t k[kUnroll], *dst[kUnroll], cur[kUnroll];
+#pragma unroll
+    for (int r = 0; r < kUnroll; ++r) {
+      const float a = ((P[0] * x[r] + P[1] * y[r]) + P[2] * z[r]) + P[3];
+      const float b = ((P[4] * x[r] + P[5] * y[r]) + P[6] * z[r]) + P[7];
+      const float w = ((P[8] * x[r] + P[9] * y[r]) + P[10] * z[r]) + P[11];
+      bool v_ok = ok[r] && w >= cam.z_near && w <= cam.z_far;
+      const float u = a / w;
+      const float v = b / w;
+      v_ok = v_ok && u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf;
+      const uint32_t j = ch.x + base + r * kThreads + threadIdx.x;
+      k[r] = ((uint64_t)__float_as_uint(w) << 32) | j;
+      dst[r] = v_ok ? key + (size_t)(uint32_t)v * cam.W + (uint32_t)u : nullptr;
+    }
+#pragma unroll
+    for (int r = 0; r < kUnroll; ++r) cur[r] = dst[r] ? *dst[r] : 0ull;
+#pragma unroll
+    for (int r = 0; r < kUnroll; ++r)
+      if (dst[r] && k[r] < cur[r]) atomicMin(reinterpret_cast<unsigned long long *>(dst[r]), (unsigned long long)k[r]);
+  }
+}
+
+// Soft z-buffer (Method, "Point Cloud Projection": colours of points at similar
+// depths are averaged).  A second pass over the same work items adds the colour
+// of every point whose depth is within (1 + eps) of its pixel's nearest depth
+// into integer sums; integer atomics make the result order independent.
+__global__ __launch_bounds__(kThreads) void soft_accum_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
+                                                              const float *__restrict__ zs,
+                                                              const uint32_t *__restrict__ rgbx,
+                                                              const uint2 *__restrict__ chunks,
+                                                              const uint32_t *__restrict__ counters, SplatCam cam,
+                                                              const uint64_t *__restrict__ key, float one_plus_eps,
+                                                              uint32_t *__restrict__ acc) {
+  if (blockIdx.x >= counters[0]) return;
+  const uint2 ch = chunks[blockIdx.x];
+  const float *P = cam.P;
   for (uint32_t i = threadIdx.x; i < ch.y; i += kThreads) {
     const uint32_t j = ch.x + i;
     const float x = xs[j], y = ys[j], z = zs[j];
@@ -112,11 +163,42 @@ __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict
     const float u = a / w;
     const float v = b / w;
     if (!(u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf)) continue;
-    const uint32_t px = (uint32_t)u, py = (uint32_t)v;
-    const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | j;
-    uint64_t *dst = key + (size_t)py * cam.W + px;
-    if (k < *dst) atomicMin(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)k);
+    const size_t p = (size_t)(uint32_t)v * cam.W + (uint32_t)u;
+    const float zmin = __uint_as_float((uint32_t)(key[p] >> 32));
+    if (!(w <= zmin * one_plus_eps)) continue;
+    const uint32_t c = rgbx[j];
+    atomicAdd(&acc[4 * p + 0], c & 255u);
+    atomicAdd(&acc[4 * p + 1], (c >> 8) & 255u);
+    atomicAdd(&acc[4 * p + 2], (c >> 16) & 255u);
+    atomicAdd(&acc[4 * p + 3], 1u);
   }
+}
+
+__global__ __launch_bounds__(kThreads) void resolve_soft_kernel(const uint64_t *__restrict__ key,
+                                                                const uint32_t *__restrict__ acc,
+                                                                float *__restrict__ depth, uint32_t *__restrict__ rgba,
+                                                                uint32_t npix) {
+  const uint32_t stride = gridDim.x * kThreads;
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < npix; i += stride) {
+    const uint64_t k = key[i];
+    if (k == ~0ull) {
+      depth[i] = 0.f;
+      rgba[i] = 0u;
+    } else {
+      depth[i] = __uint_as_float((uint32_t)(k >> 32));
+      const uint4 s = *reinterpret_cast<const uint4 *>(acc + 4ull * i);
+      const uint64_t n2 = 2ull * s.w;
+      const uint32_t r = (uint32_t)((2ull * s.x + s.w) / n2);
+      const uint32_t g = (uint32_t)((2ull * s.y + s.w) / n2);
+      const uint32_t b = (uint32_t)((2ull * s.z + s.w) / n2);
+      rgba[i] = r | (g << 8) | (b << 16) | (1u << 24);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void clear_acc_kernel(uint4 *__restrict__ acc, uint32_t npix) {
+  const uint32_t stride = gridDim.x * kThreads;
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < npix; i += stride) acc[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 __global__ __launch_bounds__(kThreads) void resolve_kernel(const uint64_t *__restrict__ key,
@@ -164,6 +246,17 @@ hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, const uint32_t *
 hipError_t launch_resolve(const uint64_t *key, const uint32_t *rgbx, float *depth, uint32_t *rgba, uint32_t npix,
                           hipStream_t s) {
   resolve_kernel<<<grid_for(npix), kThreads, 0, s>>>(key, rgbx, depth, rgba, npix);
+  return hipGetLastError();
+}
+
+hipError_t launch_soft(const CloudDev &c, const uint2 *chunks, const uint32_t *counters, const SplatCam &cam,
+                       const uint64_t *key, float one_plus_eps, uint32_t *acc, float *depth, uint32_t *rgba,
+                       uint32_t npix, hipStream_t s) {
+  clear_acc_kernel<<<grid_for(npix), kThreads, 0, s>>>(reinterpret_cast<uint4 *>(acc), npix);
+  if (c.max_chunks)
+    soft_accum_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, c.rgbx, chunks, counters, cam, key,
+                                                         one_plus_eps, acc);
+  resolve_soft_kernel<<<grid_for(npix), kThreads, 0, s>>>(key, acc, depth, rgba, npix);
   return hipGetLastError();
 }
 

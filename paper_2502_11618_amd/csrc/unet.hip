@@ -48,6 +48,9 @@ struct ConvArgs {
   int cout, cin_pad;
   void *out;
   void *out_pool;
+  const float *head_w;
+  const float *head_b;
+  float *head_out;
 };
 
 // LDS layout: per tile pixel, CK channels plus padding that staggers pixels
@@ -130,34 +133,55 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     __syncthreads();
 
     // ---- K loop over the 9 taps and the staged channels ----
+    if (MODE == 0) {
+      // float32: steps it = (tap, 8-channel group); the operands of step it + 1
+      // are loaded (weights from global/L1, activations from LDS) while the
+      // MFMAs of step it run
+      constexpr int G = CK / 8;
+      constexpr int NIT = 9 * G;
+      const float *wp = static_cast<const float *>(a.w);
+      const float *sp = reinterpret_cast<const float *>(&s_in[0][0]);
+      const float *wrow[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) wrow[mb] = wp + (size_t)(co0 + mb * 32 + n) * 9 * a.cin_pad + ci + 4 * h;
+      auto load = [&](int it, float4 *av, float4 *bv) {
+        const int tap = it / G, g = it - tap * G;
+        const int dy = tap / 3, dx = tap - 3 * dy;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+          av[mb] = *reinterpret_cast<const float4 *>(wrow[mb] + tap * a.cin_pad + g * 8);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          bv[nb] = *reinterpret_cast<const float4 *>(sp + ((pr + dy) * kLW + (nb * 16 + pc + dx)) * S + g * 8 + 4 * h);
+      };
+      auto mma = [&](const float4 *av, const float4 *bv) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][i], bv[nb][i], acc[mb][nb], 0, 0, 0);
+      };
+      float4 a0[MB], b0[2], a1[MB], b1[2];
+      load(0, a0, b0);
+#pragma unroll 1
+      for (int it = 0; it < NIT; it += 2) {
+        if (it + 1 < NIT) load(it + 1, a1, b1);
+        mma(a0, b0);
+        if (it + 1 < NIT) {
+          if (it + 2 < NIT) load(it + 2, a0, b0);
+          mma(a1, b1);
+        }
+      }
+    } else {
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap - 3 * (tap / 3);
       int boff[2];
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) boff[nb] = ((pr + dy) * kLW + (nb * 16 + pc + dx)) * S;
-      if (MODE == 0) {
-        const float *wp = static_cast<const float *>(a.w);
-#pragma unroll
-        for (int g = 0; g < CK / 8; ++g) {
-          float4 av[MB], bv[2];
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-            av[mb] = *reinterpret_cast<const float4 *>(
-                wp + ((size_t)(co0 + mb * 32 + n) * 9 + tap) * a.cin_pad + ci + g * 8 + 4 * h);
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb)
-            bv[nb] = *reinterpret_cast<const float4 *>(
-                reinterpret_cast<const float *>(&s_in[0][0]) + boff[nb] + g * 8 + 4 * h);
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-              for (int nb = 0; nb < 2; ++nb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][i], bv[nb][i], acc[mb][nb], 0, 0, 0);
-        }
-      } else {
+      {
         const uint16_t *wp = static_cast<const uint16_t *>(a.w);
         const uint16_t *wl = static_cast<const uint16_t *>(a.w_lo);
 #pragma unroll
@@ -190,11 +214,46 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         }
       }
     }
+    }
     __syncthreads();
   }
 
-  // ---- epilogue: bias + ReLU, store NHWC, optional fused 2x2 max-pool ----
+  // ---- epilogue ----
   // accumulator register r = 4j + i holds output channel 8j + 4h + i of the block
+  if (a.head_out) {
+    // fused 1x1 head: this block holds every output channel of its pixels; each
+    // lane sums its 16 channels per M block, the other half-wave adds the rest
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int gy = ty0 + pr, gx = tx0 + nb * 16 + pc;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = co0 + mb * 32 + 8 * j + 4 * h + i;
+            if (c < a.cout) {
+              const float v = fmaxf(acc[mb][nb][4 * j + i] + a.bias[c], 0.f);
+              s0 = fmaf(a.head_w[c], v, s0);
+              s1 = fmaf(a.head_w[a.cout + c], v, s1);
+              s2 = fmaf(a.head_w[2 * a.cout + c], v, s2);
+            }
+          }
+      s0 += __shfl_xor(s0, 32, 64);
+      s1 += __shfl_xor(s1, 32, 64);
+      s2 += __shfl_xor(s2, 32, 64);
+      if (h == 0 && gy < H && gx < W) {
+        const size_t HW = (size_t)H * W, p = (size_t)gy * W + gx;
+        a.head_out[p] = s0 + a.head_b[0];
+        a.head_out[HW + p] = s1 + a.head_b[1];
+        a.head_out[2 * HW + p] = s2 + a.head_b[2];
+      }
+    }
+    return;
+  }
+  // bias + ReLU, store NHWC, optional fused 2x2 max-pool
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
@@ -337,7 +396,9 @@ hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, in
 
 hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s) {
   const ConvLayer &L = *c.layer;
-  ConvArgs a{c.in0, c.in1, c.C0, c.C1, c.H, c.W, L.w, L.w_lo, L.bias, L.cout, L.cin_pad, c.out, c.out_pool};
+  ConvArgs a{c.in0, c.in1, c.C0, c.C1, c.H, c.W, L.w, L.w_lo, L.bias, L.cout, L.cin_pad, c.out, c.out_pool,
+             c.head_w, c.head_b, c.head_out};
+  if (c.head_out && (L.cout_pad > 64 || c.out_pool)) return hipErrorInvalidValue;
   const int step = (p == Prec::F32) ? 8 : 16;
   int ck = 32;
   while (ck > step && ((c.C0 % ck) != 0 || (c.C1 % ck) != 0)) ck >>= 1;

@@ -54,11 +54,31 @@ class lnr_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("ms", ctypes.c_float)]
 
 
+def _hip_runtimes():
+    """Distinct HIP runtime libraries mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return paths
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2502_11618_amd.build` "
                           "(there is no fallback implementation)")
+    # torch ships its own HIP runtime under the same soname; loading it first makes
+    # liblnr.so bind to that same runtime, so torch's streams and device pointers
+    # are valid in the library (two runtimes in one process do not share devices).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
+    rt = _hip_runtimes()
+    if len(rt) > 1:
+        raise ImportError(f"more than one HIP runtime is loaded ({sorted(rt)}); import torch before liblnr.so")
     vp, u64, i32, f32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_float
     sig = {
         "lnr_context_create": (i32, [ctypes.c_int, u64, ctypes.POINTER(vp)]),

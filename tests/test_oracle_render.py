@@ -131,3 +131,52 @@ def test_camera_at_scanner_sees_first_hits(room_scene):
     wbits = (k[valid] >> np.uint64(32)).astype(np.uint32).view(np.float32)
     assert np.all(depth[pix[valid]] <= wbits)
     assert np.all(rgba[pix[valid], 3] == 1)
+
+
+def test_soft_zbuffer_closed_forms():
+    """Two points in one pixel at depths 2.0 and 2.01: with eps = 0.01 both join
+    (2.01 <= 2.02) and the colour is their rounded mean; with eps = 0.001 only
+    the nearest counts; eps = 0 with equal depths averages the tie."""
+    cam = synth.look_at([0, 0, 0], [1, 0, 0], 16, 16, 90.0)
+    xyz = np.float32([[2.0, 0.01, 0.01], [2.01, 0.0101, 0.0101], [2.0, 0.012, 0.011]])
+    rgb = np.array([[10, 20, 31], [21, 40, 60], [200, 100, 0]], np.uint8)
+    key = R.splat(xyz[:2, 0], xyz[:2, 1], xyz[:2, 2], cam.P, 16, 16, 0.1, 1000.0)
+    (p,) = np.nonzero(key != EMPTY)
+    soft = R.soft_colors(xyz[:2, 0], xyz[:2, 1], xyz[:2, 2], rgb[:2], cam.P, 16, 16, 0.1, 1000.0, key, 0.01)
+    # (10 + 21) / 2 = 15.5 -> 16, (20 + 40) / 2 = 30, (31 + 60) / 2 = 45.5 -> 46
+    assert soft[p[0]].tolist() == [16, 30, 46, 1]
+    soft = R.soft_colors(xyz[:2, 0], xyz[:2, 1], xyz[:2, 2], rgb[:2], cam.P, 16, 16, 0.1, 1000.0, key, 0.001)
+    assert soft[p[0]].tolist() == [10, 20, 31, 1]
+    key3 = R.splat(xyz[:, 0], xyz[:, 1], xyz[:, 2], cam.P, 16, 16, 0.1, 1000.0)
+    soft = R.soft_colors(xyz[:, 0], xyz[:, 1], xyz[:, 2], rgb, cam.P, 16, 16, 0.1, 1000.0, key3, 0.0)
+    # points 0 and 2 tie at depth 2.0: (10+200)/2 = 105, (20+100)/2 = 60, (31+0)/2 = 15.5 -> 16
+    assert soft[p[0]].tolist() == [105, 60, 16, 1]
+
+
+def test_soft_zbuffer_brute_force():
+    """Per pixel: average of every point landing there within (1 + eps) of the
+    nearest depth, searched exhaustively in float64 on a cloud kept off pixel
+    borders and with depth gaps far from the threshold."""
+    rng = np.random.default_rng(4)
+    cam = synth.look_at([0, 0, 0], [10, 0, 0], 12, 10, 60.0)
+    xyz = _cloud_off_borders(rng, cam, 600, zrange=(2.0, 3.0))
+    rgb = rng.integers(0, 256, xyz.shape, dtype=np.uint8)
+    u, v, w = _project64(xyz, cam)
+    key = R.splat(xyz[:, 0], xyz[:, 1], xyz[:, 2], cam.P, 12, 10, cam.z_near, cam.z_far)
+    eps = 0.05
+    soft = R.soft_colors(xyz[:, 0], xyz[:, 1], xyz[:, 2], rgb, cam.P, 12, 10, cam.z_near, cam.z_far, key, eps)
+    for py in range(10):
+        for px in range(12):
+            idx = [j for j in range(len(xyz)) if int(np.floor(u[j])) == px and int(np.floor(v[j])) == py]
+            got = soft[py * 12 + px]
+            if not idx:
+                assert got.tolist() == [0, 0, 0, 0]
+                continue
+            zmin = min(w[j] for j in idx)
+            near = [j for j in idx if w[j] <= zmin * (1 + eps) * (1 - 1e-6)]
+            far = [j for j in idx if w[j] > zmin * (1 + eps) * (1 + 1e-6)]
+            if len(near) + len(far) != len(idx):
+                continue  # a depth within rounding of the threshold
+            s = rgb[near].astype(np.int64).sum(0)
+            want = (2 * s + len(near)) // (2 * len(near))
+            assert got[:3].tolist() == want.tolist() and got[3] == 1
