@@ -136,6 +136,16 @@ void lnr_cloud_destroy(lnr_cloud *c);
  * LNR_RENDER_NO_CULL. */
 lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out, uint32_t flags,
                       void *hip_stream);
+/* Render with the soft z-buffer of Method, "Point Cloud Projection" (colours of
+ * points that arrive at similar depths are averaged, given a small depth
+ * threshold).  As lnr_render, except that a filled pixel's rgb is, per
+ * channel, the integer sum over every point landing on it whose float32 depth
+ * w satisfies w <= zmin * (1 + soft_eps) (zmin = depth of its nearest point,
+ * which still gives key and depth), divided by their count and rounded half
+ * up.  soft_eps >= 0 and finite.  Uses 16 bytes of context scratch per pixel;
+ * a pixel may collect at most 2^24 points. */
+lnr_status lnr_render_soft(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out,
+                           float soft_eps, uint32_t flags, void *hip_stream);
 /* Statistics of the last lnr_render on ctx; waits for ctx's last stream.
  * visible_cells: cells that passed the frustum test; processed_points:
  * points in those cells.  cull_flags_host (may be NULL): HOST uint8[n_cells]
@@ -192,6 +202,62 @@ typedef struct {
 } lnr_kernel_time;
 lnr_status lnr_profile_enable(lnr_context *ctx, int enable);
 lnr_status lnr_profile_read(lnr_context *ctx, lnr_kernel_time *out, int32_t max, int32_t *count);
+
+/* ---------------------------------------------------------------------------
+ * Serving: many viewer sessions rendering the same resident cloud.
+ *
+ * Sessions are opened with their resolution; a session's image and output
+ * buffers are allocated from the context's budget when it opens, so a session
+ * that does not fit is refused with LNR_E_BUDGET (admission by HBM budget).
+ * Each submitted camera becomes a request.  lnr_server_step takes a free lane
+ * (a HIP stream with its own scratch) and the oldest pending request, joins it
+ * with up to max_batch - 1 other pending requests of the same resolution, and
+ * enqueues for them: render (or soft render), depth filter, and one batched
+ * U-Net over all of them (each convolution processes the whole batch in one
+ * launch; the launch sequence of every (resolution, batch size) is captured
+ * once as a HIP graph and replayed).  Lanes run concurrently, so batches
+ * overlap on the device.  A session has at most one request in flight; a
+ * newer camera submitted while the older one is still pending replaces it
+ * (the older is reported as superseded).  Every image is computed exactly as
+ * lnr_render + lnr_depth_filter + lnr_reconstruct would compute it alone.
+ * The server and its sessions are externally synchronised (one host thread).
+ * ------------------------------------------------------------------------- */
+typedef struct lnr_server lnr_server;
+typedef struct {
+  int32_t max_batch;        /* 1..16 requests of one resolution per batch          */
+  int32_t lanes;            /* 1..8 concurrent HIP streams                          */
+  int32_t n_levels;         /* depth filter levels (0 = unfiltered input)           */
+  float filter_strength;    /* depth filter strength                                */
+  int32_t soft;             /* non-zero: soft z-buffer with soft_eps                */
+  float soft_eps;
+  int32_t use_graphs;       /* non-zero: replay captured HIP graphs for the U-Net   */
+  int32_t max_width, max_height; /* largest session resolution (sizes lane scratch) */
+} lnr_server_config;
+typedef struct {
+  int32_t session;
+  uint64_t tag;             /* the caller's tag of the request                      */
+  int32_t superseded;       /* 1: replaced by a newer camera before it ran          */
+  int32_t batch;            /* requests in the batch that computed it               */
+  float batch_gpu_ms;       /* device time of that whole batch                      */
+  const float *rgb;         /* DEVICE float[3*H*W]; valid until the session's       */
+                            /* request after next completes                         */
+  int32_t width, height;
+} lnr_server_result;
+/* The U-Net must have widths[0] <= 64 (its head is fused into the last
+ * convolution, which lets one launch write every session's output). */
+lnr_status lnr_server_create(lnr_context *ctx, const lnr_cloud *c, const lnr_unet *u, const lnr_server_config *cfg,
+                             lnr_server **out);
+void lnr_server_destroy(lnr_server *srv); /* waits for its lanes; NULL-safe */
+lnr_status lnr_server_open_session(lnr_server *srv, int32_t width, int32_t height, int32_t *session);
+lnr_status lnr_server_close_session(lnr_server *srv, int32_t session); /* waits for its request */
+lnr_status lnr_server_submit(lnr_server *srv, int32_t session, const lnr_camera *cam, uint64_t tag);
+/* Enqueue at most one batch on a free lane; *launched = requests enqueued (0 if
+ * no lane is free or nothing is pending).  Never waits for the device. */
+lnr_status lnr_server_step(lnr_server *srv, int32_t *launched);
+/* Finished and superseded requests since the last poll (non-blocking). */
+lnr_status lnr_server_poll(lnr_server *srv, lnr_server_result *out, int32_t max, int32_t *count);
+/* Requests pending (not yet launched) and in flight. */
+lnr_status lnr_server_pending(const lnr_server *srv, int32_t *pending, int32_t *in_flight);
 
 #ifdef __cplusplus
 }

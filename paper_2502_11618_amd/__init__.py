@@ -3,10 +3,21 @@ LiDAR Point Clouds" (arXiv 2502.11618): grid culling, 1x1 point projection
 into RGBDA, hierarchical min-pool depth filter and U-Net reconstruction, as a
 C-ABI library of hand-written HIP kernels (liblnr.so) with a ctypes binding.
 
-Importing the package loads liblnr.so and fails loudly if it is not built.
+The binding (paper_2502_11618_amd.lnr) loads liblnr.so on first use of any of
+its names and fails loudly if the library is not built; importing the
+package itself does not load it, so `paper_2502_11618_amd.build` can run on
+a fresh checkout.
 """
 
-from .lnr import *  # noqa: F401,F403
-from .lnr import (  # noqa: F401
-    Cloud, Context, Image, LnrError, UNet, camera_struct, lnr_camera, lnr_image, LIB_PATH,
-)
+import importlib
+
+
+_SUBMODULES = ("lnr", "build")
+
+
+def __getattr__(name):
+    if name.startswith("__"):
+        raise AttributeError(name)
+    if name in _SUBMODULES:
+        return importlib.import_module(f"{__name__}.{name}")
+    return getattr(importlib.import_module(__name__ + ".lnr"), name)

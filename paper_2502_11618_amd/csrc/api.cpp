@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <deque>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -25,6 +28,11 @@ struct Buf {
 
 thread_local std::string g_create_error;
 
+// device scratch reused by consecutive calls on one stream
+struct Scratch {
+  Buf flags, chunks, counters, pyramid, act, soft_acc;
+};
+
 }  // namespace
 
 struct lnr_context {
@@ -35,7 +43,7 @@ struct lnr_context {
   hipStream_t last_stream = nullptr;
   bool rendered = false;
   uint32_t last_cells = 0;
-  Buf flags, chunks, counters, pyramid, act;
+  Scratch sc;
   // kernel timing
   struct Rec {
     const char *name;
@@ -252,6 +260,143 @@ float host_bf2f(uint16_t h) {
   return f;
 }
 
+
+// ---------------------------------------------------------------------------
+// U-Net activation layout for a batch of B same-shape images, and its launches
+// ---------------------------------------------------------------------------
+struct UNetLayout {
+  int H = 0, W = 0, B = 1;
+  size_t es = 4;  // bytes per activation element
+  size_t x0_off = 0, x0_bs = 0;
+  size_t t_off[6] = {}, s_off[6] = {}, p_off[6] = {}, d_off[6] = {};
+  size_t act_bs[6] = {}, pool_bs[6] = {};  // per-image elements at level l (w_l and w_{l-1} channels)
+  size_t bytes = 0;
+};
+
+UNetLayout unet_layout(const lnr_unet *u, int H, int W, int B) {
+  UNetLayout y;
+  y.H = H;
+  y.W = W;
+  y.B = B;
+  y.es = (u->prec == Prec::BF16) ? 2 : 4;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  size_t off = 0;
+  y.x0_bs = (size_t)H * W * u->cin0_pad;
+  y.x0_off = off;
+  off += al(y.x0_bs * B * y.es);
+  for (int l = 0; l < u->L; ++l) {
+    const size_t px = (size_t)(H >> l) * (W >> l);
+    y.act_bs[l] = px * u->widths[l];
+    y.pool_bs[l] = (l > 0) ? px * u->widths[l - 1] : 0;
+    y.t_off[l] = off;
+    off += al(y.act_bs[l] * B * y.es);
+    y.s_off[l] = off;
+    off += al(y.act_bs[l] * B * y.es);
+    y.d_off[l] = off;
+    off += al(y.act_bs[l] * B * y.es);
+    y.p_off[l] = off;
+    off += al(y.pool_bs[l] * B * y.es);
+  }
+  y.bytes = off;
+  return y;
+}
+
+lnr_status unet_pack(lnr_context *ctx, Scratch &sc, const lnr_unet *u, const UNetLayout &y, int b, const float *depth,
+                     const uint32_t *rgba, hipStream_t s) {
+  char *x0 = static_cast<char *>(sc.act.p) + y.x0_off + (size_t)b * y.x0_bs * y.es;
+  LNR_LAUNCH(ctx, "pack", s, launch_pack_input(depth, rgba, y.H, y.W, u->cin0_pad, u->prec, x0, s));
+  return LNR_OK;
+}
+
+// All 3x3 convolutions of the network over the batch; the 1x1 head is fused
+// into the last one when widths[0] <= 64 (outputs: head_outs_dev[b] if given,
+// else rgb_out + b * 3*H*W), otherwise it runs as its own kernel per image.
+lnr_status unet_convs(lnr_context *ctx, Scratch &sc, const lnr_unet *u, const UNetLayout &y, float *rgb_out,
+                      float *const *head_outs_dev, hipStream_t s) {
+  char *base = static_cast<char *>(sc.act.p);
+  const int L = u->L, B = y.B;
+  const bool fuse_head = u->widths[0] <= 64;
+  if (!fuse_head && head_outs_dev) return fail(ctx, LNR_E_UNSUPPORTED, "batched outputs need widths[0] <= 64");
+  int li = 0;
+  for (int l = 0; l < L; ++l) {
+    const int Hl = y.H >> l, Wl = y.W >> l;
+    ConvCall a{};
+    a.in0 = (l == 0) ? (const void *)(base + y.x0_off) : (const void *)(base + y.p_off[l]);
+    a.C0 = (l == 0) ? u->cin0_pad : u->widths[l - 1];
+    a.in0_bs = (l == 0) ? y.x0_bs : y.pool_bs[l];
+    a.in1 = nullptr;
+    a.C1 = 0;
+    a.H = Hl;
+    a.W = Wl;
+    a.layer = &u->convs[li++];
+    a.out = base + y.t_off[l];
+    a.out_bs = y.act_bs[l];
+    a.batch = B;
+    LNR_LAUNCH(ctx, kConvNames[0][l][0], s, launch_conv3x3(a, u->prec, s));
+    ConvCall c{};
+    c.in0 = base + y.t_off[l];
+    c.C0 = u->widths[l];
+    c.in0_bs = y.act_bs[l];
+    c.H = Hl;
+    c.W = Wl;
+    c.layer = &u->convs[li++];
+    c.out = base + y.s_off[l];
+    c.out_bs = y.act_bs[l];
+    c.out_pool = (l < L - 1) ? (void *)(base + y.p_off[l + 1]) : nullptr;
+    c.pool_bs = (l < L - 1) ? y.pool_bs[l + 1] : 0;
+    c.batch = B;
+    if (L == 1 && fuse_head) {
+      c.head_w = static_cast<const float *>(u->head.w);
+      c.head_b = u->head.bias;
+      c.head_out = rgb_out;
+      c.head_outs = head_outs_dev;
+    }
+    LNR_LAUNCH(ctx, kConvNames[0][l][1], s, launch_conv3x3(c, u->prec, s));
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const int Hl = y.H >> l, Wl = y.W >> l;
+    ConvCall a{};
+    a.in0 = base + y.s_off[l];
+    a.C0 = u->widths[l];
+    a.in0_bs = y.act_bs[l];
+    a.in1 = (l == L - 2) ? (const void *)(base + y.s_off[L - 1]) : (const void *)(base + y.d_off[l + 1]);
+    a.C1 = u->widths[l + 1];
+    a.in1_bs = y.act_bs[l + 1];
+    a.H = Hl;
+    a.W = Wl;
+    a.layer = &u->convs[li++];
+    a.out = base + y.t_off[l];
+    a.out_bs = y.act_bs[l];
+    a.batch = B;
+    LNR_LAUNCH(ctx, kConvNames[1][l][0], s, launch_conv3x3(a, u->prec, s));
+    ConvCall c{};
+    c.in0 = base + y.t_off[l];
+    c.C0 = u->widths[l];
+    c.in0_bs = y.act_bs[l];
+    c.H = Hl;
+    c.W = Wl;
+    c.layer = &u->convs[li++];
+    c.out = base + y.d_off[l];
+    c.out_bs = y.act_bs[l];
+    c.batch = B;
+    if (l == 0 && fuse_head) {
+      c.head_w = static_cast<const float *>(u->head.w);
+      c.head_b = u->head.bias;
+      c.head_out = rgb_out;
+      c.head_outs = head_outs_dev;
+    }
+    LNR_LAUNCH(ctx, kConvNames[1][l][1], s, launch_conv3x3(c, u->prec, s));
+  }
+  if (!fuse_head) {
+    const size_t off = (L == 1) ? y.s_off[0] : y.d_off[0];
+    for (int b = 0; b < B; ++b)
+      LNR_LAUNCH(ctx, "head", s,
+                 launch_head(base + off + (size_t)b * y.act_bs[0] * y.es, u->widths[0], y.H, y.W, u->head, u->prec,
+                             rgb_out + (size_t)b * 3 * y.H * y.W, s));
+  }
+  return LNR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -292,7 +437,8 @@ void lnr_context_destroy(lnr_context *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  for (Buf *b : {&ctx->flags, &ctx->chunks, &ctx->counters, &ctx->pyramid, &ctx->act}) dfree(ctx, b->p, b->cap);
+  for (Buf *b : {&ctx->sc.flags, &ctx->sc.chunks, &ctx->sc.counters, &ctx->sc.pyramid, &ctx->sc.act, &ctx->sc.soft_acc})
+    dfree(ctx, b->p, b->cap);
   for (auto &r : ctx->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -457,9 +603,11 @@ void lnr_cloud_destroy(lnr_cloud *c) {
 // ---------------------------------------------------------------------------
 // render
 // ---------------------------------------------------------------------------
-lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out, uint32_t flags,
-                      void *hip_stream) {
+static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c, const lnr_camera *cam,
+                              lnr_image *out, uint32_t flags, bool soft, float soft_eps, void *hip_stream) {
   if (!ctx) return LNR_E_INVALID_ARG;
+  if (soft && !(std::isfinite(soft_eps) && soft_eps >= 0.f))
+    return fail(ctx, LNR_E_INVALID_ARG, "soft_eps must be finite and >= 0");
   if (!c || !cam || !out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
   if (flags & ~LNR_RENDER_NO_CULL) return fail(ctx, LNR_E_INVALID_ARG, "unknown render flags");
   std::string why;
@@ -473,11 +621,11 @@ lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *ca
   lnr_status st = use_device(ctx);
   if (st != LNR_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if ((st = ensure(ctx, ctx->flags, c->d.n_cells)) != LNR_OK) return st;
-  if ((st = ensure(ctx, ctx->chunks, 8ull * std::max<uint32_t>(1, c->d.max_chunks))) != LNR_OK) return st;
-  if ((st = ensure(ctx, ctx->counters, 256)) != LNR_OK) return st;
+  if ((st = ensure(ctx, scr.flags, c->d.n_cells)) != LNR_OK) return st;
+  if ((st = ensure(ctx, scr.chunks, 8ull * std::max<uint32_t>(1, c->d.max_chunks))) != LNR_OK) return st;
+  if ((st = ensure(ctx, scr.counters, 256)) != LNR_OK) return st;
   const uint32_t npix = (uint32_t)cam->width * (uint32_t)cam->height;
-  uint32_t *counters = static_cast<uint32_t *>(ctx->counters.p);
+  uint32_t *counters = static_cast<uint32_t *>(scr.counters.p);
   const CullParams prm = make_cull_params(cam, (flags & LNR_RENDER_NO_CULL) != 0);
   SplatCam sc{};
   std::memcpy(sc.P, cam->P, sizeof(sc.P));
@@ -487,14 +635,33 @@ lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *ca
   sc.z_far = cam->z_far;
   sc.W = (uint32_t)cam->width;
   LNR_LAUNCH(ctx, "clear", s, launch_clear(out->key, npix, counters, s));
-  LNR_LAUNCH(ctx, "cull", s, launch_cull(c->d, prm, static_cast<uint8_t *>(ctx->flags.p), static_cast<uint2 *>(ctx->chunks.p),
+  LNR_LAUNCH(ctx, "cull", s, launch_cull(c->d, prm, static_cast<uint8_t *>(scr.flags.p), static_cast<uint2 *>(scr.chunks.p),
                            counters, s));
-  LNR_LAUNCH(ctx, "splat", s, launch_splat(c->d, static_cast<const uint2 *>(ctx->chunks.p), counters, sc, out->key, s));
-  LNR_LAUNCH(ctx, "resolve", s, launch_resolve(out->key, c->d.rgbx, out->depth, reinterpret_cast<uint32_t *>(out->rgba), npix, s));
+  LNR_LAUNCH(ctx, "splat", s, launch_splat(c->d, static_cast<const uint2 *>(scr.chunks.p), counters, sc, out->key, s));
+  if (soft) {
+    if ((st = ensure(ctx, scr.soft_acc, 16ull * npix)) != LNR_OK) return st;
+    LNR_LAUNCH(ctx, "soft", s,
+               launch_soft(c->d, static_cast<const uint2 *>(scr.chunks.p), counters, sc, out->key, 1.0f + soft_eps,
+                           static_cast<uint32_t *>(scr.soft_acc.p), out->depth, reinterpret_cast<uint32_t *>(out->rgba),
+                           npix, s));
+  } else {
+    LNR_LAUNCH(ctx, "resolve", s,
+               launch_resolve(out->key, c->d.rgbx, out->depth, reinterpret_cast<uint32_t *>(out->rgba), npix, s));
+  }
   ctx->last_stream = s;
   ctx->rendered = true;
   ctx->last_cells = c->d.n_cells;
   return LNR_OK;
+}
+
+lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out, uint32_t flags,
+                      void *hip_stream) {
+  return render_impl(ctx, ctx->sc, c, cam, out, flags, false, 0.f, hip_stream);
+}
+
+lnr_status lnr_render_soft(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out,
+                           float soft_eps, uint32_t flags, void *hip_stream) {
+  return render_impl(ctx, ctx->sc, c, cam, out, flags, true, soft_eps, hip_stream);
 }
 
 lnr_status lnr_render_stats(lnr_context *ctx, uint64_t *visible_cells, uint64_t *processed_points,
@@ -505,19 +672,28 @@ lnr_status lnr_render_stats(lnr_context *ctx, uint64_t *visible_cells, uint64_t 
   if (st != LNR_OK) return st;
   LNR_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
   uint32_t cnt[kCounterWords];
-  LNR_HIP(ctx, hipMemcpy(cnt, ctx->counters.p, sizeof(cnt), hipMemcpyDeviceToHost));
+  LNR_HIP(ctx, hipMemcpy(cnt, ctx->sc.counters.p, sizeof(cnt), hipMemcpyDeviceToHost));
   if (visible_cells) *visible_cells = cnt[1];
   if (processed_points) *processed_points = (uint64_t)cnt[2] | ((uint64_t)cnt[3] << 32);
   if (cull_flags_host)
-    LNR_HIP(ctx, hipMemcpy(cull_flags_host, ctx->flags.p, ctx->last_cells, hipMemcpyDeviceToHost));
+    LNR_HIP(ctx, hipMemcpy(cull_flags_host, ctx->sc.flags.p, ctx->last_cells, hipMemcpyDeviceToHost));
   return LNR_OK;
 }
 
 // ---------------------------------------------------------------------------
 // depth filter
 // ---------------------------------------------------------------------------
+static lnr_status depth_filter_impl(lnr_context *ctx, Scratch &scr, lnr_image *io, int32_t n_levels,
+                                    float filter_strength, void *hip_stream);
+
 lnr_status lnr_depth_filter(lnr_context *ctx, lnr_image *io, int32_t n_levels, float filter_strength,
                             void *hip_stream) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  return depth_filter_impl(ctx, ctx->sc, io, n_levels, filter_strength, hip_stream);
+}
+
+static lnr_status depth_filter_impl(lnr_context *ctx, Scratch &scr, lnr_image *io, int32_t n_levels,
+                                    float filter_strength, void *hip_stream) {
   if (!ctx) return LNR_E_INVALID_ARG;
   if (!io || !io->depth || !io->rgba) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
   if (io->width < 1 || io->height < 1 || io->width > 16384 || io->height > 16384)
@@ -550,8 +726,8 @@ lnr_status lnr_depth_filter(lnr_context *ctx, lnr_image *io, int32_t n_levels, f
     uoffs[k] = total;
     total += ((size_t)Hs[k] * Ws[k] * 4 + 255) / 256 * 256;
   }
-  if ((st = ensure(ctx, ctx->pyramid, total)) != LNR_OK) return st;
-  char *base = static_cast<char *>(ctx->pyramid.p);
+  if ((st = ensure(ctx, scr.pyramid, total)) != LNR_OK) return st;
+  char *base = static_cast<char *>(scr.pyramid.p);
   float *D[32] = {nullptr}, *U[32] = {nullptr};
   for (int k = 1; k <= n_levels; ++k) D[k] = reinterpret_cast<float *>(base + offs[k]);
   for (int k = 1; k < n_levels; ++k) U[k] = reinterpret_cast<float *>(base + uoffs[k]);
@@ -738,91 +914,12 @@ lnr_status lnr_reconstruct(lnr_context *ctx, const lnr_unet *u, const lnr_image 
     return fail(ctx, LNR_E_INVALID_ARG, "misaligned buffers");
   lnr_status st = use_device(ctx);
   if (st != LNR_OK) return st;
-  const size_t es = (u->prec == Prec::BF16) ? 2 : 4;
-  // activation buffers: x0, and per level t, s, p (pooled input), d
-  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  size_t off = 0;
-  const size_t x0_off = off;
-  off += al((size_t)H * W * u->cin0_pad * es);
-  size_t t_off[6], s_off[6], p_off[6], d_off[6];
-  for (int l = 0; l < L; ++l) {
-    const size_t px = (size_t)(H >> l) * (W >> l);
-    t_off[l] = off;
-    off += al(px * u->widths[l] * es);
-    s_off[l] = off;
-    off += al(px * u->widths[l] * es);
-    d_off[l] = off;
-    off += al(px * u->widths[l] * es);
-    p_off[l] = off;
-    off += (l > 0) ? al(px * u->widths[l - 1] * es) : 0;
-  }
-  if ((st = ensure(ctx, ctx->act, off)) != LNR_OK) return st;
-  char *base = static_cast<char *>(ctx->act.p);
+  const UNetLayout lay = unet_layout(u, H, W, 1);
+  if ((st = ensure(ctx, ctx->sc.act, lay.bytes)) != LNR_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  LNR_LAUNCH(ctx, "pack", s, launch_pack_input(in->depth, reinterpret_cast<const uint32_t *>(in->rgba), H, W, u->cin0_pad, u->prec,
-                                 base + x0_off, s));
-  // the 1x1 head runs in the epilogue of the last 3x3 convolution when one
-  // workgroup holds all of its output channels
-  const bool fuse_head = u->widths[0] <= 64;
-  int li = 0;
-  for (int l = 0; l < L; ++l) {
-    const int Hl = H >> l, Wl = W >> l;
-    ConvCall a{};
-    a.in0 = (l == 0) ? (const void *)(base + x0_off) : (const void *)(base + p_off[l]);
-    a.C0 = (l == 0) ? u->cin0_pad : u->widths[l - 1];
-    a.in1 = nullptr;
-    a.C1 = 0;
-    a.H = Hl;
-    a.W = Wl;
-    a.layer = &u->convs[li++];
-    a.out = base + t_off[l];
-    a.out_pool = nullptr;
-    LNR_LAUNCH(ctx, kConvNames[0][l][0], s, launch_conv3x3(a, u->prec, s));
-    ConvCall b{};
-    b.in0 = base + t_off[l];
-    b.C0 = u->widths[l];
-    b.H = Hl;
-    b.W = Wl;
-    b.layer = &u->convs[li++];
-    b.out = base + s_off[l];
-    b.out_pool = (l < L - 1) ? (void *)(base + p_off[l + 1]) : nullptr;
-    if (L == 1 && fuse_head) {
-      b.head_w = static_cast<const float *>(u->head.w);
-      b.head_b = u->head.bias;
-      b.head_out = rgb_out;
-    }
-    LNR_LAUNCH(ctx, kConvNames[0][l][1], s, launch_conv3x3(b, u->prec, s));
-  }
-  for (int l = L - 2; l >= 0; --l) {
-    const int Hl = H >> l, Wl = W >> l;
-    ConvCall a{};
-    a.in0 = base + s_off[l];
-    a.C0 = u->widths[l];
-    a.in1 = (l == L - 2) ? (const void *)(base + s_off[L - 1]) : (const void *)(base + d_off[l + 1]);
-    a.C1 = u->widths[l + 1];
-    a.H = Hl;
-    a.W = Wl;
-    a.layer = &u->convs[li++];
-    a.out = base + t_off[l];
-    LNR_LAUNCH(ctx, kConvNames[1][l][0], s, launch_conv3x3(a, u->prec, s));
-    ConvCall b{};
-    b.in0 = base + t_off[l];
-    b.C0 = u->widths[l];
-    b.H = Hl;
-    b.W = Wl;
-    b.layer = &u->convs[li++];
-    b.out = base + d_off[l];
-    if (l == 0 && fuse_head) {
-      b.head_w = static_cast<const float *>(u->head.w);
-      b.head_b = u->head.bias;
-      b.head_out = rgb_out;
-    }
-    LNR_LAUNCH(ctx, kConvNames[1][l][1], s, launch_conv3x3(b, u->prec, s));
-  }
-  if (!fuse_head) {
-    const void *last = (L == 1) ? (const void *)(base + s_off[0]) : (const void *)(base + d_off[0]);
-    LNR_LAUNCH(ctx, "head", s, launch_head(last, u->widths[0], H, W, u->head, u->prec, rgb_out, s));
-  }
+  if ((st = unet_pack(ctx, ctx->sc, u, lay, 0, in->depth, reinterpret_cast<const uint32_t *>(in->rgba), s)) != LNR_OK)
+    return st;
+  if ((st = unet_convs(ctx, ctx->sc, u, lay, rgb_out, nullptr, s)) != LNR_OK) return st;
   ctx->last_stream = s;
   return LNR_OK;
 }
@@ -862,4 +959,377 @@ lnr_status lnr_profile_read(lnr_context *ctx, lnr_kernel_time *out, int32_t max,
   return LNR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// serving
+// ---------------------------------------------------------------------------
 }  // extern "C"
+
+namespace {
+
+struct ServerSession {
+  bool open = false;
+  int W = 0, H = 0;
+  void *buf = nullptr;
+  size_t bytes = 0;
+  uint64_t *key = nullptr;
+  float *depth = nullptr;
+  uint8_t *rgba = nullptr;
+  float *out[2] = {nullptr, nullptr};
+  int next_out = 0;
+  bool pending = false;
+  bool in_flight = false;
+  lnr_camera cam{};
+  uint64_t tag = 0;
+  uint64_t seq = 0;  // submission order of the pending request
+};
+
+struct ServerLane {
+  hipStream_t stream = nullptr;
+  Scratch sc;
+  hipEvent_t ev_start = nullptr, ev_done = nullptr;
+  bool busy = false;
+  std::vector<int> sess;
+  std::vector<uint64_t> tags;
+  std::vector<const float *> outs;
+  float **head_outs_dev = nullptr;   // device array [max_batch]
+  float **head_outs_host = nullptr;  // pinned host staging of the same
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_defs;
+};
+
+}  // namespace
+
+struct lnr_server {
+  lnr_context *ctx = nullptr;
+  const lnr_cloud *cloud = nullptr;
+  const lnr_unet *unet = nullptr;
+  lnr_server_config cfg{};
+  std::vector<ServerSession> sessions;
+  std::vector<ServerLane> lanes;
+  std::deque<lnr_server_result> done;
+  uint64_t seq = 0;
+};
+
+namespace {
+
+void server_release(lnr_server *srv) {
+  lnr_context *ctx = srv->ctx;
+  for (auto &l : srv->lanes) {
+    if (l.stream) (void)hipStreamSynchronize(l.stream);
+    for (auto &g : l.graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto g : l.graph_defs) (void)hipGraphDestroy(g);
+    for (Buf *b : {&l.sc.flags, &l.sc.chunks, &l.sc.counters, &l.sc.pyramid, &l.sc.act, &l.sc.soft_acc})
+      dfree(ctx, b->p, b->cap);
+    if (l.head_outs_dev) dfree(ctx, l.head_outs_dev, 8ull * 16);
+    if (l.head_outs_host) (void)hipHostFree(l.head_outs_host);
+    if (l.ev_start) (void)hipEventDestroy(l.ev_start);
+    if (l.ev_done) (void)hipEventDestroy(l.ev_done);
+    if (l.stream) (void)hipStreamDestroy(l.stream);
+  }
+  srv->lanes.clear();
+  for (auto &ss : srv->sessions)
+    if (ss.buf) dfree(ctx, ss.buf, ss.bytes);
+  srv->sessions.clear();
+}
+
+// move a finished lane's requests to the done list
+void server_collect(lnr_server *srv, ServerLane &l) {
+  if (!l.busy || hipEventQuery(l.ev_done) != hipSuccess) return;
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, l.ev_start, l.ev_done);
+  for (size_t i = 0; i < l.sess.size(); ++i) {
+    ServerSession &ss = srv->sessions[l.sess[i]];
+    ss.in_flight = false;
+    lnr_server_result r{};
+    r.session = l.sess[i];
+    r.tag = l.tags[i];
+    r.superseded = 0;
+    r.batch = (int32_t)l.sess.size();
+    r.batch_gpu_ms = ms;
+    r.rgb = l.outs[i];
+    r.width = ss.W;
+    r.height = ss.H;
+    srv->done.push_back(r);
+  }
+  l.sess.clear();
+  l.tags.clear();
+  l.outs.clear();
+  l.busy = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+lnr_status lnr_server_create(lnr_context *ctx, const lnr_cloud *c, const lnr_unet *u, const lnr_server_config *cfg,
+                             lnr_server **out) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!c || !u || !cfg || !out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
+  *out = nullptr;
+  if (cfg->max_batch < 1 || cfg->max_batch > 16) return fail(ctx, LNR_E_INVALID_ARG, "max_batch must be in [1, 16]");
+  if (cfg->lanes < 1 || cfg->lanes > 8) return fail(ctx, LNR_E_INVALID_ARG, "lanes must be in [1, 8]");
+  if (cfg->max_width < 1 || cfg->max_height < 1 || cfg->max_width > 16384 || cfg->max_height > 16384)
+    return fail(ctx, LNR_E_INVALID_ARG, "bad max resolution");
+  if (cfg->soft && !(std::isfinite(cfg->soft_eps) && cfg->soft_eps >= 0.f))
+    return fail(ctx, LNR_E_INVALID_ARG, "soft_eps must be finite and >= 0");
+  if (std::isnan(cfg->filter_strength) || cfg->filter_strength < 0.f || cfg->n_levels < 0)
+    return fail(ctx, LNR_E_INVALID_ARG, "bad depth filter parameters");
+  if (u->widths[0] > 64) return fail(ctx, LNR_E_UNSUPPORTED, "serving needs a U-Net with widths[0] <= 64");
+  const int a = 1 << (u->L - 1);
+  const int mW = (cfg->max_width + a - 1) / a * a, mH = (cfg->max_height + a - 1) / a * a;
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  std::unique_ptr<lnr_server> srv(new lnr_server);
+  srv->ctx = ctx;
+  srv->cloud = c;
+  srv->unet = u;
+  srv->cfg = *cfg;
+  srv->lanes.resize(cfg->lanes);
+  // every lane's scratch is sized for the largest resolution and batch up front,
+  // so captured graphs keep pointing at live buffers
+  const size_t npix = (size_t)mW * mH;
+  size_t pyr = 0;
+  {
+    int h = mH, w = mW;
+    for (int k = 1; k <= std::max(cfg->n_levels, 1); ++k) {
+      h = (h + 1) / 2;
+      w = (w + 1) / 2;
+      pyr += 2 * (((size_t)h * w * 4 + 255) / 256 * 256);
+    }
+  }
+  const size_t act = unet_layout(u, mH, mW, cfg->max_batch).bytes;
+  for (auto &l : srv->lanes) {
+    hipError_t e = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&l.ev_start);
+    if (e == hipSuccess) e = hipEventCreate(&l.ev_done);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&l.head_outs_host, 8ull * 16, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      server_release(srv.get());
+      return hip_fail(ctx, e, "server lane setup");
+    }
+    if ((st = ensure(ctx, l.sc.flags, c->d.n_cells)) != LNR_OK ||
+        (st = ensure(ctx, l.sc.chunks, 8ull * std::max<uint32_t>(1, c->d.max_chunks))) != LNR_OK ||
+        (st = ensure(ctx, l.sc.counters, 256)) != LNR_OK || (st = ensure(ctx, l.sc.pyramid, pyr)) != LNR_OK ||
+        (st = ensure(ctx, l.sc.act, act)) != LNR_OK ||
+        (cfg->soft && (st = ensure(ctx, l.sc.soft_acc, 16 * npix)) != LNR_OK) ||
+        (st = dalloc(ctx, (void **)&l.head_outs_dev, 8ull * 16)) != LNR_OK) {
+      server_release(srv.get());
+      return st;
+    }
+  }
+  *out = srv.release();
+  return LNR_OK;
+}
+
+void lnr_server_destroy(lnr_server *srv) {
+  if (!srv) return;
+  (void)hipSetDevice(srv->ctx->device);
+  server_release(srv);
+  delete srv;
+}
+
+lnr_status lnr_server_open_session(lnr_server *srv, int32_t width, int32_t height, int32_t *session) {
+  if (!srv || !session) return srv ? fail(srv->ctx, LNR_E_INVALID_ARG, "NULL pointer argument") : LNR_E_INVALID_ARG;
+  lnr_context *ctx = srv->ctx;
+  const int a = 1 << (srv->unet->L - 1);
+  if (width < 1 || height < 1 || width > srv->cfg.max_width || height > srv->cfg.max_height || width % a ||
+      height % a)
+    return fail(ctx, LNR_E_INVALID_ARG, "session size must be within the server's maximum and divisible by 2^(L-1)");
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  const size_t np = (size_t)width * height;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t bytes = al(8 * np) + al(4 * np) + al(4 * np) + 2 * al(12 * np);
+  ServerSession ss;
+  if ((st = dalloc(ctx, &ss.buf, bytes)) != LNR_OK) return st;  // LNR_E_BUDGET: not admitted
+  ss.bytes = bytes;
+  char *p = static_cast<char *>(ss.buf);
+  ss.key = reinterpret_cast<uint64_t *>(p);
+  p += al(8 * np);
+  ss.depth = reinterpret_cast<float *>(p);
+  p += al(4 * np);
+  ss.rgba = reinterpret_cast<uint8_t *>(p);
+  p += al(4 * np);
+  ss.out[0] = reinterpret_cast<float *>(p);
+  p += al(12 * np);
+  ss.out[1] = reinterpret_cast<float *>(p);
+  ss.open = true;
+  ss.W = width;
+  ss.H = height;
+  for (size_t i = 0; i < srv->sessions.size(); ++i)
+    if (!srv->sessions[i].open && !srv->sessions[i].buf) {
+      srv->sessions[i] = ss;
+      *session = (int32_t)i;
+      return LNR_OK;
+    }
+  srv->sessions.push_back(ss);
+  *session = (int32_t)srv->sessions.size() - 1;
+  return LNR_OK;
+}
+
+lnr_status lnr_server_close_session(lnr_server *srv, int32_t session) {
+  if (!srv) return LNR_E_INVALID_ARG;
+  lnr_context *ctx = srv->ctx;
+  if (session < 0 || session >= (int32_t)srv->sessions.size() || !srv->sessions[session].open)
+    return fail(ctx, LNR_E_INVALID_ARG, "no such session");
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  for (auto &l : srv->lanes)
+    if (l.busy && std::find(l.sess.begin(), l.sess.end(), session) != l.sess.end()) {
+      LNR_HIP(ctx, hipEventSynchronize(l.ev_done));
+      server_collect(srv, l);
+    }
+  ServerSession &ss = srv->sessions[session];
+  dfree(ctx, ss.buf, ss.bytes);
+  ss = ServerSession();
+  return LNR_OK;
+}
+
+lnr_status lnr_server_submit(lnr_server *srv, int32_t session, const lnr_camera *cam, uint64_t tag) {
+  if (!srv) return LNR_E_INVALID_ARG;
+  lnr_context *ctx = srv->ctx;
+  if (!cam) return fail(ctx, LNR_E_INVALID_ARG, "NULL camera");
+  if (session < 0 || session >= (int32_t)srv->sessions.size() || !srv->sessions[session].open)
+    return fail(ctx, LNR_E_INVALID_ARG, "no such session");
+  ServerSession &ss = srv->sessions[session];
+  std::string why;
+  if (!camera_ok(cam, &why)) return fail(ctx, LNR_E_INVALID_ARG, why);
+  if (cam->width != ss.W || cam->height != ss.H) return fail(ctx, LNR_E_INVALID_ARG, "camera size differs from the session's");
+  if (ss.pending) {
+    lnr_server_result r{};
+    r.session = session;
+    r.tag = ss.tag;
+    r.superseded = 1;
+    r.width = ss.W;
+    r.height = ss.H;
+    srv->done.push_back(r);
+  }
+  ss.pending = true;
+  ss.cam = *cam;
+  ss.tag = tag;
+  ss.seq = srv->seq++;
+  return LNR_OK;
+}
+
+lnr_status lnr_server_step(lnr_server *srv, int32_t *launched) {
+  if (!srv || !launched) return srv ? fail(srv->ctx, LNR_E_INVALID_ARG, "NULL pointer argument") : LNR_E_INVALID_ARG;
+  lnr_context *ctx = srv->ctx;
+  *launched = 0;
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  ServerLane *lane = nullptr;
+  for (auto &l : srv->lanes) {
+    server_collect(srv, l);
+    if (!l.busy && !lane) lane = &l;
+  }
+  if (!lane) return LNR_OK;
+  // the oldest runnable request decides the resolution of the batch
+  int first = -1;
+  for (size_t i = 0; i < srv->sessions.size(); ++i) {
+    const ServerSession &ss = srv->sessions[i];
+    if (ss.open && ss.pending && !ss.in_flight && (first < 0 || ss.seq < srv->sessions[first].seq)) first = (int)i;
+  }
+  if (first < 0) return LNR_OK;
+  const int W = srv->sessions[first].W, H = srv->sessions[first].H;
+  std::vector<int> batch;
+  {
+    std::vector<std::pair<uint64_t, int>> cand;
+    for (size_t i = 0; i < srv->sessions.size(); ++i) {
+      const ServerSession &ss = srv->sessions[i];
+      if (ss.open && ss.pending && !ss.in_flight && ss.W == W && ss.H == H) cand.emplace_back(ss.seq, (int)i);
+    }
+    std::sort(cand.begin(), cand.end());
+    for (size_t i = 0; i < cand.size() && (int)batch.size() < srv->cfg.max_batch; ++i) batch.push_back(cand[i].second);
+  }
+  const int B = (int)batch.size();
+  hipStream_t s = lane->stream;
+  const bool was_profiling = ctx->profiling;
+  ctx->profiling = false;
+  LNR_HIP(ctx, hipEventRecord(lane->ev_start, s));
+  const UNetLayout lay = unet_layout(srv->unet, H, W, B);
+  for (int b = 0; b < B; ++b) {
+    ServerSession &ss = srv->sessions[batch[b]];
+    lnr_image img{ss.key, ss.depth, ss.rgba, ss.W, ss.H};
+    st = render_impl(ctx, lane->sc, srv->cloud, &ss.cam, &img, 0, srv->cfg.soft != 0, srv->cfg.soft_eps, s);
+    if (st == LNR_OK && srv->cfg.n_levels > 0)
+      st = depth_filter_impl(ctx, lane->sc, &img, srv->cfg.n_levels, srv->cfg.filter_strength, s);
+    if (st == LNR_OK) st = unet_pack(ctx, lane->sc, srv->unet, lay, b, ss.depth, reinterpret_cast<const uint32_t *>(ss.rgba), s);
+    if (st != LNR_OK) {
+      ctx->profiling = was_profiling;
+      return st;
+    }
+    float *o = ss.out[ss.next_out];
+    ss.next_out ^= 1;
+    lane->head_outs_host[b] = o;
+    lane->outs.push_back(o);
+  }
+  LNR_HIP(ctx, hipMemcpyAsync(lane->head_outs_dev, lane->head_outs_host, 8ull * B, hipMemcpyHostToDevice, s));
+  if (srv->cfg.use_graphs) {
+    const auto key = std::make_tuple(H, W, B);
+    auto it = lane->graphs.find(key);
+    if (it == lane->graphs.end()) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ge = nullptr;
+      LNR_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      st = unet_convs(ctx, lane->sc, srv->unet, lay, nullptr, lane->head_outs_dev, s);
+      hipError_t e = hipStreamEndCapture(s, &g);
+      if (st != LNR_OK) {
+        ctx->profiling = was_profiling;
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+      LNR_HIP(ctx, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      lane->graph_defs.push_back(g);
+      it = lane->graphs.emplace(key, ge).first;
+    }
+    LNR_HIP(ctx, hipGraphLaunch(it->second, s));
+  } else {
+    st = unet_convs(ctx, lane->sc, srv->unet, lay, nullptr, lane->head_outs_dev, s);
+    if (st != LNR_OK) {
+      ctx->profiling = was_profiling;
+      return st;
+    }
+  }
+  ctx->profiling = was_profiling;
+  LNR_HIP(ctx, hipEventRecord(lane->ev_done, s));
+  for (int b = 0; b < B; ++b) {
+    ServerSession &ss = srv->sessions[batch[b]];
+    ss.pending = false;
+    ss.in_flight = true;
+    lane->sess.push_back(batch[b]);
+    lane->tags.push_back(ss.tag);
+  }
+  lane->busy = true;
+  *launched = B;
+  return LNR_OK;
+}
+
+lnr_status lnr_server_poll(lnr_server *srv, lnr_server_result *out, int32_t max, int32_t *count) {
+  if (!srv || !count || (max > 0 && !out)) return srv ? fail(srv->ctx, LNR_E_INVALID_ARG, "bad arguments") : LNR_E_INVALID_ARG;
+  lnr_status st = use_device(srv->ctx);
+  if (st != LNR_OK) return st;
+  for (auto &l : srv->lanes) server_collect(srv, l);
+  int32_t n = 0;
+  while (n < max && !srv->done.empty()) {
+    out[n++] = srv->done.front();
+    srv->done.pop_front();
+  }
+  *count = n;
+  return LNR_OK;
+}
+
+lnr_status lnr_server_pending(const lnr_server *srv, int32_t *pending, int32_t *in_flight) {
+  if (!srv) return LNR_E_INVALID_ARG;
+  int32_t p = 0, f = 0;
+  for (const auto &ss : srv->sessions) {
+    p += (ss.open && ss.pending) ? 1 : 0;
+    f += (ss.open && ss.in_flight) ? 1 : 0;
+  }
+  if (pending) *pending = p;
+  if (in_flight) *in_flight = f;
+  return LNR_OK;
+}
+
+}  // extern "C"
+

@@ -117,6 +117,11 @@ struct ConvCall {
   const float *head_w = nullptr;  // [3][cout]
   const float *head_b = nullptr;  // [3]
   float *head_out = nullptr;      // planar float [3][H][W]
+  // batch of same-shape images (per-image element strides; head_outs: device
+  // array of per-image head outputs, or null for head_out + image * 3*H*W)
+  int batch = 1;
+  size_t in0_bs = 0, in1_bs = 0, out_bs = 0, pool_bs = 0;
+  float *const *head_outs = nullptr;
 };
 
 hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, int W, int cpad, Prec p, void *x,

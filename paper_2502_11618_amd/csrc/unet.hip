@@ -51,6 +51,12 @@ struct ConvArgs {
   const float *head_w;
   const float *head_b;
   float *head_out;
+  // batch of same-shape images: blockIdx.z = image * (cout_pad / BM) + channel tile;
+  // per-image element strides of the tensors above; head_outs (device array) gives
+  // each image's planar head output when set
+  int batch;
+  size_t in0_bs, in1_bs, out_bs, pool_bs;
+  float *const *head_outs;
 };
 
 // LDS layout: per tile pixel, CK channels plus padding that staggers pixels
@@ -73,9 +79,18 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = lane & 31, h = lane >> 5;
   const int ty0 = blockIdx.y * kTH, tx0 = blockIdx.x * kTW;
-  const int co0 = blockIdx.z * BM;
+  const int nzc = gridDim.z / a.batch;
+  const int bimg = blockIdx.z / nzc;
+  const int co0 = (blockIdx.z - bimg * nzc) * BM;
   const int H = a.H, W = a.W;
   const int Cin = a.C0 + a.C1;
+  // this image's tensors (element type in HBM: bf16 bits for BF16, float otherwise)
+  using E = typename std::conditional<MODE == 1, uint16_t, float>::type;
+  const E *in0 = static_cast<const E *>(a.in0) + (size_t)bimg * a.in0_bs;
+  const E *in1 = a.in1 ? static_cast<const E *>(a.in1) + (size_t)bimg * a.in1_bs : nullptr;
+  E *out = a.out ? static_cast<E *>(a.out) + (size_t)bimg * a.out_bs : nullptr;
+  E *out_pool = a.out_pool ? static_cast<E *>(a.out_pool) + (size_t)bimg * a.pool_bs : nullptr;
+  float *head_out = a.head_outs ? a.head_outs[bimg] : (a.head_out ? a.head_out + (size_t)bimg * 3 * H * W : nullptr);
 
   floatx16 acc[MB][2];
 #pragma unroll
@@ -105,7 +120,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         gi = from0 ? ((size_t)gy * W + gx) * csrc + coff + q * VEC
                    : ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * csrc + coff + q * VEC;
       }
-      const void *src = from0 ? a.in0 : a.in1;
+      const void *src = from0 ? (const void *)in0 : (const void *)in1;
       if (MODE == 0) {
         float4 v = inside ? *reinterpret_cast<const float4 *>(static_cast<const float *>(src) + gi)
                           : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -220,7 +235,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 
   // ---- epilogue ----
   // accumulator register r = 4j + i holds output channel 8j + 4h + i of the block
-  if (a.head_out) {
+  if (head_out) {
     // fused 1x1 head: this block holds every output channel of its pixels; each
     // lane sums its 16 channels per M block, the other half-wave adds the rest
 #pragma unroll
@@ -246,9 +261,9 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
       s2 += __shfl_xor(s2, 32, 64);
       if (h == 0 && gy < H && gx < W) {
         const size_t HW = (size_t)H * W, p = (size_t)gy * W + gx;
-        a.head_out[p] = s0 + a.head_b[0];
-        a.head_out[HW + p] = s1 + a.head_b[1];
-        a.head_out[2 * HW + p] = s2 + a.head_b[2];
+        head_out[p] = s0 + a.head_b[0];
+        head_out[HW + p] = s1 + a.head_b[1];
+        head_out[2 * HW + p] = s2 + a.head_b[2];
       }
     }
     return;
@@ -272,14 +287,14 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) b16[i] = f2bf(v[i]);
           if (store)
-            *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(a.out) + ((size_t)gy * W + gx) * a.cout + c) =
+            *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(out) + ((size_t)gy * W + gx) * a.cout + c) =
                 make_uint2(b16[0] | ((uint32_t)b16[1] << 16), b16[2] | ((uint32_t)b16[3] << 16));
         } else {
           if (store)
-            *reinterpret_cast<float4 *>(static_cast<float *>(a.out) + ((size_t)gy * W + gx) * a.cout + c) =
+            *reinterpret_cast<float4 *>(reinterpret_cast<float *>(out) + ((size_t)gy * W + gx) * a.cout + c) =
                 make_float4(v[0], v[1], v[2], v[3]);
         }
-        if (a.out_pool) {
+        if (out_pool) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             v[i] = fmaxf(v[i], __shfl_xor(v[i], 1, 64));
@@ -291,10 +306,10 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
               uint16_t b16[4];
 #pragma unroll
               for (int i = 0; i < 4; ++i) b16[i] = f2bf(v[i]);
-              *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(a.out_pool) + pi) =
+              *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(out_pool) + pi) =
                   make_uint2(b16[0] | ((uint32_t)b16[1] << 16), b16[2] | ((uint32_t)b16[3] << 16));
             } else {
-              *reinterpret_cast<float4 *>(static_cast<float *>(a.out_pool) + pi) = make_float4(v[0], v[1], v[2], v[3]);
+              *reinterpret_cast<float4 *>(reinterpret_cast<float *>(out_pool) + pi) = make_float4(v[0], v[1], v[2], v[3]);
             }
           }
         }
@@ -362,7 +377,7 @@ __global__ __launch_bounds__(256) void head_kernel(const void *__restrict__ x, i
 
 template <int MODE, int BM, int CK>
 hipError_t conv_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
-  dim3 grid((a.W + kTW - 1) / kTW, (a.H + kTH - 1) / kTH, cout_pad / BM);
+  dim3 grid((a.W + kTW - 1) / kTW, (a.H + kTH - 1) / kTH, (cout_pad / BM) * a.batch);
   conv3x3_kernel<MODE, BM, CK><<<grid, 256, 0, s>>>(a);
   return hipGetLastError();
 }
@@ -397,7 +412,8 @@ hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, in
 hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s) {
   const ConvLayer &L = *c.layer;
   ConvArgs a{c.in0, c.in1, c.C0, c.C1, c.H, c.W, L.w, L.w_lo, L.bias, L.cout, L.cin_pad, c.out, c.out_pool,
-             c.head_w, c.head_b, c.head_out};
+             c.head_w, c.head_b, c.head_out, c.batch < 1 ? 1 : c.batch, c.in0_bs, c.in1_bs, c.out_bs, c.pool_bs,
+             c.head_outs};
   if (c.head_out && (L.cout_pad > 64 || c.out_pool)) return hipErrorInvalidValue;
   const int step = (p == Prec::F32) ? 8 : 16;
   int ck = 32;

@@ -54,6 +54,18 @@ class lnr_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("ms", ctypes.c_float)]
 
 
+class lnr_server_config(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("lanes", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("filter_strength", ctypes.c_float), ("soft", ctypes.c_int32), ("soft_eps", ctypes.c_float),
+                ("use_graphs", ctypes.c_int32), ("max_width", ctypes.c_int32), ("max_height", ctypes.c_int32)]
+
+
+class lnr_server_result(ctypes.Structure):
+    _fields_ = [("session", ctypes.c_int32), ("tag", ctypes.c_uint64), ("superseded", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("batch_gpu_ms", ctypes.c_float), ("rgb", ctypes.c_void_p),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
 def _hip_runtimes():
     """Distinct HIP runtime libraries mapped into this process."""
     paths = set()
@@ -92,6 +104,8 @@ def _load():
         "lnr_cloud_cell_start": (i32, [vp, vp]),
         "lnr_cloud_destroy": (None, [vp]),
         "lnr_render": (i32, [vp, vp, ctypes.POINTER(lnr_camera), ctypes.POINTER(lnr_image), ctypes.c_uint32, vp]),
+        "lnr_render_soft": (i32, [vp, vp, ctypes.POINTER(lnr_camera), ctypes.POINTER(lnr_image), f32, ctypes.c_uint32,
+                                  vp]),
         "lnr_render_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), vp]),
         "lnr_depth_filter": (i32, [vp, ctypes.POINTER(lnr_image), i32, f32, vp]),
         "lnr_unet_load": (i32, [vp, vp, u64, ctypes.c_int, ctypes.POINTER(vp)]),
@@ -100,6 +114,14 @@ def _load():
         "lnr_sync": (i32, [vp, vp]),
         "lnr_profile_enable": (i32, [vp, ctypes.c_int]),
         "lnr_profile_read": (i32, [vp, ctypes.POINTER(lnr_kernel_time), i32, ctypes.POINTER(i32)]),
+        "lnr_server_create": (i32, [vp, vp, vp, ctypes.POINTER(lnr_server_config), ctypes.POINTER(vp)]),
+        "lnr_server_destroy": (None, [vp]),
+        "lnr_server_open_session": (i32, [vp, i32, i32, ctypes.POINTER(i32)]),
+        "lnr_server_close_session": (i32, [vp, i32]),
+        "lnr_server_submit": (i32, [vp, i32, ctypes.POINTER(lnr_camera), u64]),
+        "lnr_server_step": (i32, [vp, ctypes.POINTER(i32)]),
+        "lnr_server_poll": (i32, [vp, ctypes.POINTER(lnr_server_result), i32, ctypes.POINTER(i32)]),
+        "lnr_server_pending": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -261,6 +283,14 @@ def lnr_render(ctx: Context, cloud: Cloud, cam, image: Image, flags: int = 0, st
            ctx.handle)
 
 
+def lnr_render_soft(ctx: Context, cloud: Cloud, cam, image: Image, soft_eps: float = 0.01, flags: int = 0,
+                    stream=None) -> None:
+    c = cam if isinstance(cam, lnr_camera) else camera_struct(cam)
+    img = image.struct()
+    _check(_lib.lnr_render_soft(ctx.handle, cloud.handle, ctypes.byref(c), ctypes.byref(img), float(soft_eps), flags,
+                                _stream(stream)), ctx.handle)
+
+
 def lnr_render_stats(ctx: Context, n_cells: Optional[int] = None):
     vis = ctypes.c_uint64()
     proc = ctypes.c_uint64()
@@ -307,3 +337,84 @@ def lnr_profile_read(ctx: Context, max_records: int = 1 << 16):
     n = ctypes.c_int32()
     _check(_lib.lnr_profile_read(ctx.handle, buf, max_records, ctypes.byref(n)), ctx.handle)
     return [(buf[i].name.decode(), float(buf[i].ms)) for i in range(min(n.value, max_records))]
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+class Server:
+    def __init__(self, ctx, handle, keep):
+        self.ctx = ctx
+        self.handle = handle
+        self._keep = keep  # the cloud and network must outlive the server
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.lnr_server_destroy(self.handle)
+            self.handle = None
+
+
+def lnr_server_create(ctx: Context, cloud: Cloud, unet: UNet, max_batch: int = 8, lanes: int = 2,
+                      n_levels: int = 5, filter_strength: float = 0.5, soft: bool = False, soft_eps: float = 0.01,
+                      use_graphs: bool = True, max_width: int = 1920, max_height: int = 1080) -> Server:
+    cfg = lnr_server_config(max_batch, lanes, n_levels, filter_strength, 1 if soft else 0, soft_eps,
+                            1 if use_graphs else 0, max_width, max_height)
+    h = ctypes.c_void_p()
+    _check(_lib.lnr_server_create(ctx.handle, cloud.handle, unet.handle, ctypes.byref(cfg), ctypes.byref(h)),
+           ctx.handle)
+    return Server(ctx, h.value, (cloud, unet))
+
+
+def lnr_server_open_session(srv: Server, width: int, height: int) -> int:
+    sid = ctypes.c_int32()
+    _check(_lib.lnr_server_open_session(srv.handle, int(width), int(height), ctypes.byref(sid)), srv.ctx.handle)
+    return sid.value
+
+
+def lnr_server_close_session(srv: Server, session: int) -> None:
+    _check(_lib.lnr_server_close_session(srv.handle, int(session)), srv.ctx.handle)
+
+
+def lnr_server_submit(srv: Server, session: int, cam, tag: int) -> None:
+    c = cam if isinstance(cam, lnr_camera) else camera_struct(cam)
+    _check(_lib.lnr_server_submit(srv.handle, int(session), ctypes.byref(c), int(tag)), srv.ctx.handle)
+
+
+def lnr_server_step(srv: Server) -> int:
+    n = ctypes.c_int32()
+    _check(_lib.lnr_server_step(srv.handle, ctypes.byref(n)), srv.ctx.handle)
+    return n.value
+
+
+def lnr_server_poll(srv: Server, max_results: int = 1024):
+    buf = (lnr_server_result * max_results)()
+    n = ctypes.c_int32()
+    _check(_lib.lnr_server_poll(srv.handle, buf, max_results, ctypes.byref(n)), srv.ctx.handle)
+    return [dict(session=r.session, tag=r.tag, superseded=bool(r.superseded), batch=r.batch,
+                 batch_gpu_ms=r.batch_gpu_ms, rgb=r.rgb, width=r.width, height=r.height) for r in buf[:n.value]]
+
+
+def lnr_server_pending(srv: Server):
+    p = ctypes.c_int32()
+    f = ctypes.c_int32()
+    _check(_lib.lnr_server_pending(srv.handle, ctypes.byref(p), ctypes.byref(f)), srv.ctx.handle)
+    return p.value, f.value
+
+
+def copy_from_device(ptr: int, out) -> None:
+    """Copy out.numel() elements from library-owned device memory at `ptr` into
+    the torch tensor `out` (hipMemcpy of the HIP runtime the library shares
+    with torch)."""
+    global _hip
+    if _hip is None:
+        (path,) = _hip_runtimes()
+        _hip = ctypes.CDLL(path)
+        _hip.hipMemcpy.restype = ctypes.c_int
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    err = _hip.hipMemcpy(out.data_ptr(), ptr, out.numel() * out.element_size(), 3)  # device to device
+    if err != 0:
+        raise LnrError(LNR_E_DEVICE, f"hipMemcpy failed ({err})")
+
+
+_hip = None

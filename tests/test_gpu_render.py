@@ -140,3 +140,26 @@ def test_render_rejects_bad_arguments(lnr, ctx, room_cloud, room_cams):
     with pytest.raises(lnr.LnrError):
         lnr.lnr_render(ctx, room_cloud, c, lnr.Image(cam.height, cam.width))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.01, 0.05])
+def test_soft_zbuffer_bit_exact(lnr, ctx, room_cloud, room_grid, room_cams, eps):
+    """The paper's soft z-buffer: colour = rounded mean over points within
+    (1 + eps) of the nearest depth; key and depth stay the nearest point's."""
+    import torch
+    g = room_grid
+    for i, cam in enumerate(room_cams[:6]):
+        img = lnr.Image(cam.height, cam.width)
+        lnr.lnr_render_soft(ctx, room_cloud, cam, img, eps)
+        torch.cuda.synchronize()
+        key, depth, _ = R.render(g, cam)
+        rgba = R.soft_colors(g.xs, g.ys, g.zs, g.rgb, cam.P, cam.width, cam.height, cam.z_near, cam.z_far, key, eps)
+        assert_images_equal(image_to_host(img), (key, depth, rgba), f"soft eps={eps} frame {i}")
+
+
+def test_soft_zbuffer_rejects_bad_eps(lnr, ctx, room_cloud, room_cams):
+    cam = room_cams[0]
+    for eps in (-0.1, float("nan"), float("inf")):
+        with pytest.raises(lnr.LnrError) as e:
+            lnr.lnr_render_soft(ctx, room_cloud, cam, lnr.Image(cam.height, cam.width), eps)
+        assert e.value.status == lnr.LNR_E_INVALID_ARG

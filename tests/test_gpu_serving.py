@@ -1,0 +1,113 @@
+"""The serving loop: every session's frame computed in a batch of mixed
+sessions equals the same frame computed alone; admission by budget; newer
+cameras supersede pending ones."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import depth_filter as F
+from oracle import metrics as M
+from oracle import render as R
+from oracle import unet as U
+from tests.gpu_util import render_gpu
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(64, 64), (128, 96), (64, 64), (128, 96), (64, 64), (96, 64), (64, 64)]
+
+
+def _alone(lnr, ctx, cloud, net, cam, n_levels, fs):
+    import torch
+    img = render_gpu(lnr, ctx, cloud, cam)
+    if n_levels:
+        lnr.lnr_depth_filter(ctx, img, n_levels, fs)
+    out = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device="cuda")
+    lnr.lnr_reconstruct(ctx, net, img, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _serve_all(lnr, srv, sids, cams_per_session, frames):
+    import torch
+    results = {}
+    for f in range(frames):
+        for i, sid in enumerate(sids):
+            lnr.lnr_server_submit(srv, sid, cams_per_session[i][f], tag=f * 100 + i)
+        got = 0
+        for _ in range(100000):
+            lnr.lnr_server_step(srv)
+            for r in lnr.lnr_server_poll(srv):
+                assert not r["superseded"]
+                out = torch.empty((3, r["height"], r["width"]), dtype=torch.float32, device="cuda")
+                lnr.copy_from_device(r["rgb"], out)
+                results[r["tag"]] = (out.cpu().numpy(), r["batch"])
+                got += 1
+            if got == len(sids):
+                break
+        assert got == len(sids), "server did not finish"
+    return results
+
+
+@pytest.mark.parametrize("prec,graphs", [(0, True), (1, True), (2, False)])
+def test_mixed_batches_equal_alone(lnr, ctx, room_scene, room_cloud, room_grid, prec, graphs):
+    blob = synth.make_unet_blob((16, 32, 64), seed=0)
+    net = lnr.lnr_unet_load(ctx, blob, prec)
+    srv = lnr.lnr_server_create(ctx, room_cloud, net, max_batch=4, lanes=2, n_levels=3, filter_strength=0.5,
+                                use_graphs=graphs, max_width=128, max_height=96)
+    sids = [lnr.lnr_server_open_session(srv, w, h) for (w, h) in SIZES]
+    cams = [synth.random_walk_path(room_scene, 3, seed=i, width=w, height=h, fov_deg=80.0)
+            for i, (w, h) in enumerate(SIZES)]
+    res = _serve_all(lnr, srv, sids, cams, 3)
+    assert max(b for _, b in res.values()) > 1, "no batch had more than one request"
+    onet = U.parse_blob(blob)
+    for f in range(3):
+        for i in range(len(SIZES)):
+            got, _ = res[f * 100 + i]
+            cam = cams[i][f]
+            alone = _alone(lnr, ctx, room_cloud, net, cam, 3, 0.5)
+            assert np.array_equal(got, alone), f"session {i} frame {f} differs from its standalone render"
+            if f == 0 and prec == 0:
+                _, depth, rgba = R.render(room_grid, cam)
+                fd, fr, _ = F.depth_filter(depth.reshape(cam.height, cam.width),
+                                           rgba.reshape(cam.height, cam.width, 4), 3, 0.5)
+                assert M.max_abs(got, U.forward(onet, fd, fr)) <= 1e-4
+
+
+def test_superseded_requests_and_admission(lnr, room_scene, room_cloud):
+    ctx = lnr.lnr_context_create(0)
+    blob = synth.make_unet_blob((16, 32, 64), seed=0)
+    net = lnr.lnr_unet_load(ctx, blob, lnr.LNR_BF16)
+    cloud = lnr.lnr_cloud_load(ctx, room_scene.xyz, room_scene.rgb, 0.5)
+    srv = lnr.lnr_server_create(ctx, cloud, net, max_batch=2, lanes=1, n_levels=3, max_width=64, max_height=64)
+    sid = lnr.lnr_server_open_session(srv, 64, 64)
+    cams = synth.random_walk_path(room_scene, 2, seed=1, width=64, height=64)
+    lnr.lnr_server_submit(srv, sid, cams[0], tag=1)
+    lnr.lnr_server_submit(srv, sid, cams[1], tag=2)   # replaces tag 1 before it runs
+    seen = {}
+    for _ in range(100000):
+        lnr.lnr_server_step(srv)
+        for r in lnr.lnr_server_poll(srv):
+            seen[r["tag"]] = r["superseded"]
+        if 2 in seen:
+            break
+    assert seen == {1: True, 2: False}
+    # admission by budget: measure what a server needs, then give a fresh context
+    # room for exactly two 64x64 sessions
+    base = lnr.lnr_allocated_bytes(ctx)
+    sess = lnr.lnr_allocated_bytes(ctx)
+    sid2 = lnr.lnr_server_open_session(srv, 64, 64)
+    per_session = lnr.lnr_allocated_bytes(ctx) - sess
+    lnr.lnr_server_close_session(srv, sid2)
+    lnr.lnr_server_close_session(srv, sid)
+    base = lnr.lnr_allocated_bytes(ctx)
+    small = lnr.lnr_context_create(0, base + int(2.5 * per_session))
+    net_s = lnr.lnr_unet_load(small, blob, lnr.LNR_BF16)
+    cloud_s = lnr.lnr_cloud_load(small, room_scene.xyz, room_scene.rgb, 0.5)
+    srv_s = lnr.lnr_server_create(small, cloud_s, net_s, max_batch=2, lanes=1, n_levels=3, max_width=64,
+                                  max_height=64)
+    lnr.lnr_server_open_session(srv_s, 64, 64)
+    lnr.lnr_server_open_session(srv_s, 64, 64)
+    with pytest.raises(lnr.LnrError) as e:
+        lnr.lnr_server_open_session(srv_s, 64, 64)
+    assert e.value.status == lnr.LNR_E_BUDGET

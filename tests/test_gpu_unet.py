@@ -106,3 +106,19 @@ def test_unet_load_rejects_malformed_blobs(lnr, ctx):
         with pytest.raises(lnr.LnrError) as e:
             lnr.lnr_unet_load(ctx, bad, lnr.LNR_FP32)
         assert e.value.status == st
+
+
+def test_unfiltered_variant(lnr, ctx, room_cloud, room_grid, room_cams):
+    """The paper's no-filter variant: the U-Net reads the unfiltered projection."""
+    import torch
+    blob = synth.make_unet_blob((16, 32, 64), seed=4)
+    onet = U.parse_blob(blob)
+    net = lnr.lnr_unet_load(ctx, blob, lnr.LNR_FP32)
+    for cam in room_cams[:4]:
+        img = render_gpu(lnr, ctx, room_cloud, cam)
+        out = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device="cuda")
+        lnr.lnr_reconstruct(ctx, net, img, out)
+        torch.cuda.synchronize()
+        _, depth, rgba = R.render(room_grid, cam)
+        ref = U.forward(onet, depth.reshape(cam.height, cam.width), rgba.reshape(cam.height, cam.width, 4))
+        assert M.max_abs(out.cpu().numpy(), ref) <= 1e-4
