@@ -207,6 +207,92 @@ def recorded_traffic(kernel):
     return t["fetch_bytes"] + t["write_bytes"]
 
 
+def serve_bench(L, scene, cloud, blob, seconds, n_sessions=64, seed=0, budget=32 << 30, max_batch=8, lanes=2):
+    """Serving: n_sessions viewers with seeded random-walk cameras at resolutions
+    drawn from {640x480, 1280x720, 1920x1080}, Poisson arrivals at U(30, 90) Hz
+    per session, bf16 U-Net, admitted under an HBM budget; continuous batching
+    of same-resolution requests across sessions.  Latency = host time from
+    submit to the poll that sees the frame finished."""
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(seed)
+    sizes = [(640, 480), (1280, 720), (1920, 1080)]
+    sctx = L.lnr_context_create(0, budget)
+    net = L.lnr_unet_load(sctx, blob, L.LNR_BF16)
+    srv = L.lnr_server_create(sctx, cloud, net, max_batch=max_batch, lanes=lanes, n_levels=5, filter_strength=0.5,
+                              use_graphs=True, max_width=1920, max_height=1080)
+    sess = []
+    refused = 0
+    for i in range(n_sessions):
+        w, h = sizes[int(rng.integers(3))]
+        rate = float(rng.uniform(30.0, 90.0))
+        try:
+            sid = L.lnr_server_open_session(srv, w, h)
+        except L.LnrError as e:
+            if e.status != L.LNR_E_BUDGET:
+                raise
+            refused += 1
+            continue
+        n_frames = int(rate * seconds * 1.5) + 8
+        cams = [L.camera_struct(c) for c in synth.random_walk_path(scene, n_frames, seed=1000 + i, width=w, height=h)]
+        sess.append({"sid": sid, "w": w, "h": h, "rate": rate, "cams": cams, "k": 0,
+                     "next": float(rng.exponential(1.0 / rate))})
+    submit_t = {}
+    lat, batches, per_res = [], [], {}
+    superseded = 0
+    submitted = 0
+    t0 = time.perf_counter()
+    tag = 0
+
+    def drain_results(now):
+        nonlocal superseded
+        for r in L.lnr_server_poll(srv):
+            t_sub, res = submit_t.pop(r["tag"])
+            if r["superseded"]:
+                superseded += 1
+                continue
+            lat.append(now - t_sub)
+            batches.append(r["batch"])
+            per_res[res] = per_res.get(res, 0) + 1
+
+    while True:
+        now = time.perf_counter() - t0
+        if now >= seconds:
+            break
+        for ss in sess:
+            while ss["next"] <= now and ss["k"] < len(ss["cams"]):
+                L.lnr_server_submit(srv, ss["sid"], ss["cams"][ss["k"]], tag)
+                submit_t[tag] = (time.perf_counter() - t0, f"{ss['w']}x{ss['h']}")
+                tag += 1
+                submitted += 1
+                ss["k"] += 1
+                ss["next"] += float(rng.exponential(1.0 / ss["rate"]))
+        while L.lnr_server_step(srv) > 0:
+            pass
+        drain_results(time.perf_counter() - t0)
+    t_end = time.perf_counter() - t0
+    for _ in range(1000000):
+        L.lnr_server_step(srv)
+        drain_results(time.perf_counter() - t0)
+        pend, infl = L.lnr_server_pending(srv)
+        if pend == 0 and infl == 0 and not submit_t:
+            break
+    elapsed = time.perf_counter() - t0
+    lat_ms = np.array(lat) * 1000.0
+    done = len(lat)
+    px = sum(int(k.split("x")[0]) * int(k.split("x")[1]) * v for k, v in per_res.items())
+    return {
+        "sessions_admitted": len(sess), "sessions_refused": refused, "seconds_of_arrivals": round(t_end, 2),
+        "requests": submitted, "completed": done, "superseded": superseded,
+        "frames_per_s": round(done / elapsed, 1), "megapixels_per_s": round(px / elapsed / 1e6, 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3) if done else None,
+                       "p99": round(float(np.percentile(lat_ms, 99)), 3) if done else None},
+        "mean_batch": round(float(np.mean(batches)), 2) if batches else None,
+        "frames_by_resolution": per_res, "budget_bytes": budget, "max_batch": max_batch, "lanes": lanes,
+        "precision": "bf16", "offered_requests_per_s": round(sum(ss["rate"] for ss in sess), 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +302,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="fp32,bf16x3,bf16")
     ap.add_argument("--no-error-check", action="store_true", help="skip the float64 error windows")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="serving run length (0 = skip)")
     ap.add_argument("--mode", default="frames", choices=["frames", "copy", "counters"],
                     help="copy: only a plain 1 GiB device copy (calibrates HBM byte counters); "
                          "counters: summarise rocprofv3 FETCH_SIZE/WRITE_SIZE csv files (no GPU)")
@@ -413,6 +500,11 @@ def main():
         line["env"]["cus"] = torch.cuda.get_device_properties(0).multi_processor_count
     except Exception:
         pass
+    if args.serve_seconds > 0:
+        log(f"serving 64 sessions for {args.serve_seconds} s ...")
+        line["serving"] = serve_bench(L, scene, cloud, blob, args.serve_seconds)
+        log(f"serving: {line['serving']['frames_per_s']} frames/s, p50 {line['serving']['latency_ms']['p50']} ms, "
+            f"p99 {line['serving']['latency_ms']['p99']} ms")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(scene, cams[0], blob, NL, FS, widths)

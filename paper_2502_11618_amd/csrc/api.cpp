@@ -100,8 +100,12 @@ hipEvent_t get_event(lnr_context *ctx) {
 }
 
 // Enqueue one launcher; with timing enabled, bracket it by events on the same stream.
+// The runtime's last-error slot is cleared first: launchers report it after
+// their launches, and an error left there by an unrelated earlier runtime call
+// on this thread must not be blamed on this kernel.
 #define LNR_LAUNCH(ctx, nm, s, expr)                                            \
   do {                                                                          \
+    (void)hipGetLastError();                                                    \
     hipEvent_t a_ = nullptr, b_ = nullptr;                                      \
     if ((ctx)->profiling) {                                                     \
       a_ = get_event(ctx);                                                      \

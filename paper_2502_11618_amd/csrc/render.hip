@@ -102,40 +102,21 @@ __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict
   if (blockIdx.x >= counters[0]) return;
   const uint2 ch = chunks[blockIdx.x];
   const float *P = cam.P;
-  // kUnroll points per thread are in flight at once: their coordinate loads,
-  // then their z-buffer reads, then their atomics.
-  constexpr int kUnroll = 4;
-  for (uint32_t base = 0; base < ch.y; base += kThreads * kUnroll) {
-    float x[kUnroll], y[kUnroll], z[kUnroll];
-    bool ok[kUnroll];
-#pragma unroll
-    for (int r = 0; r < kUnroll; ++r) {
-      const uint32_t i = base + r * kThreads + threadIdx.x;
-      ok[r] = i < ch.y;
-      const uint32_t j = ch.x + (ok[r] ? i : 0u);
-      x[r] = xs[j];
-      y[r] = ys[j];
-      z[r] = zs[j];
-    }
-    uint64_t k[kUnroll], *dst[kUnroll], cur[kUnroll];
-#pragma unroll
-    for (int r = 0; r < kUnroll; ++r) {
-      const float a = ((P[0] * x[r] + P[1] * y[r]) + P[2] * z[r]) + P[3];
-      const float b = ((P[4] * x[r] + P[5] * y[r]) + P[6] * z[r]) + P[7];
-      const float w = ((P[8] * x[r] + P[9] * y[r]) + P[10] * z[r]) + P[11];
-      bool v_ok = ok[r] && w >= cam.z_near && w <= cam.z_far;
-      const float u = a / w;
-      const float v = b / w;
-      v_ok = v_ok && u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf;
-      const uint32_t j = ch.x + base + r * kThreads + threadIdx.x;
-      k[r] = ((uint64_t)__float_as_uint(w) << 32) | j;
-      dst[r] = v_ok ? key + (size_t)(uint32_t)v * cam.W + (uint32_t)u : nullptr;
-    }
-#pragma unroll
-    for (int r = 0; r < kUnroll; ++r) cur[r] = dst[r] ? *dst[r] : 0ull;
-#pragma unroll
-    for (int r = 0; r < kUnroll; ++r)
-      if (dst[r] && k[r] < cur[r]) atomicMin(reinterpret_cast<unsigned long long *>(dst[r]), (unsigned long long)k[r]);
+  // (keeping several points per thread in flight was measured slower: the
+  // kernel is bound by the z-buffer atomics, not by load latency)
+  for (uint32_t i = threadIdx.x; i < ch.y; i += kThreads) {
+    const uint32_t j = ch.x + i;
+    const float x = xs[j], y = ys[j], z = zs[j];
+    const float a = ((P[0] * x + P[1] * y) + P[2] * z) + P[3];
+    const float b = ((P[4] * x + P[5] * y) + P[6] * z) + P[7];
+    const float w = ((P[8] * x + P[9] * y) + P[10] * z) + P[11];
+    if (!(w >= cam.z_near && w <= cam.z_far)) continue;
+    const float u = a / w;
+    const float v = b / w;
+    if (!(u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf)) continue;
+    const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | j;
+    uint64_t *dst = key + (size_t)(uint32_t)v * cam.W + (uint32_t)u;
+    if (k < *dst) atomicMin(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)k);
   }
 }
 

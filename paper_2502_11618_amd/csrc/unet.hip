@@ -25,9 +25,8 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kTH = 8;    // output tile rows
-constexpr int kTW = 32;   // output tile columns
-constexpr int kLH = kTH + 2, kLW = kTW + 2, kLPix = kLH * kLW;
+constexpr int kTH = 8;    // output tile rows (4 waves x 2 rows)
+// output tile columns = 16 x NB: each wave owns NB blocks of 2 rows x 16 pixels
 
 __device__ inline uint16_t f2bf(float f) {  // round to nearest even (finite inputs)
   uint32_t u = __float_as_uint(f);
@@ -68,12 +67,14 @@ struct Lds {
   static constexpr int kArrays = (MODE == 2) ? 2 : 1;
 };
 
-template <int MODE, int BM, int CK>
+template <int MODE, int BM, int CK, int NB>
 __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   using L = Lds<MODE, CK>;
   using T = typename L::T;
   constexpr int S = L::kStride;
   constexpr int MB = BM / 32;
+  constexpr int kTW = 16 * NB;
+  constexpr int kLW = kTW + 2, kLPix = (kTH + 2) * kLW;
   __shared__ __attribute__((aligned(16))) T s_in[L::kArrays][kLPix * S];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -92,11 +93,11 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   E *out_pool = a.out_pool ? static_cast<E *>(a.out_pool) + (size_t)bimg * a.pool_bs : nullptr;
   float *head_out = a.head_outs ? a.head_outs[bimg] : (a.head_out ? a.head_out + (size_t)bimg * 3 * H * W : nullptr);
 
-  floatx16 acc[MB][2];
+  floatx16 acc[MB][NB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.f;
 
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         for (int mb = 0; mb < MB; ++mb)
           av[mb] = *reinterpret_cast<const float4 *>(wrow[mb] + tap * a.cin_pad + g * 8);
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+        for (int nb = 0; nb < NB; ++nb)
           bv[nb] = *reinterpret_cast<const float4 *>(sp + ((pr + dy) * kLW + (nb * 16 + pc + dx)) * S + g * 8 + 4 * h);
       };
       auto mma = [&](const float4 *av, const float4 *bv) {
@@ -175,10 +176,10 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
+            for (int nb = 0; nb < NB; ++nb)
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][i], bv[nb][i], acc[mb][nb], 0, 0, 0);
       };
-      float4 a0[MB], b0[2], a1[MB], b1[2];
+      float4 a0[MB], b0[NB], a1[MB], b1[NB];
       load(0, a0, b0);
 #pragma unroll 1
       for (int it = 0; it < NIT; it += 2) {
@@ -193,15 +194,15 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap - 3 * (tap / 3);
-      int boff[2];
+      int boff[NB];
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) boff[nb] = ((pr + dy) * kLW + (nb * 16 + pc + dx)) * S;
+      for (int nb = 0; nb < NB; ++nb) boff[nb] = ((pr + dy) * kLW + (nb * 16 + pc + dx)) * S;
       {
         const uint16_t *wp = static_cast<const uint16_t *>(a.w);
         const uint16_t *wl = static_cast<const uint16_t *>(a.w_lo);
 #pragma unroll
         for (int g = 0; g < CK / 16; ++g) {
-          uint4 ah[MB], al[MB], bh[2], bl[2];
+          uint4 ah[MB], al[MB], bh[NB], bl[NB];
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb) {
             const size_t wi = ((size_t)(co0 + mb * 32 + n) * 9 + tap) * a.cin_pad + ci + g * 16 + 8 * h;
@@ -209,14 +210,14 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
             if (MODE == 2) al[mb] = *reinterpret_cast<const uint4 *>(wl + wi);
           }
 #pragma unroll
-          for (int nb = 0; nb < 2; ++nb) {
+          for (int nb = 0; nb < NB; ++nb) {
             bh[nb] = *reinterpret_cast<const uint4 *>(&s_in[0][boff[nb] + g * 16 + 8 * h]);
             if (MODE == 2) bl[nb] = *reinterpret_cast<const uint4 *>(&s_in[MODE == 2 ? 1 : 0][boff[nb] + g * 16 + 8 * h]);
           }
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
+            for (int nb = 0; nb < NB; ++nb) {
               if (MODE == 2) {
                 acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(al[mb]), as_bf16x8(bh[nb]),
                                                                       acc[mb][nb], 0, 0, 0);
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     // fused 1x1 head: this block holds every output channel of its pixels; each
     // lane sums its 16 channels per M block, the other half-wave adds the rest
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
+    for (int nb = 0; nb < NB; ++nb) {
       const int gy = ty0 + pr, gx = tx0 + nb * 16 + pc;
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
 #pragma unroll
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
+    for (int nb = 0; nb < NB; ++nb) {
       const int gy = ty0 + pr, gx = tx0 + nb * 16 + pc;
       const bool inside = gy < H && gx < W;
 #pragma unroll
@@ -375,25 +376,52 @@ __global__ __launch_bounds__(256) void head_kernel(const void *__restrict__ x, i
   out[2 * (size_t)npix + p] = y2;
 }
 
-template <int MODE, int BM, int CK>
+template <int MODE, int BM, int CK, int NB>
 hipError_t conv_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
+  constexpr int kTW = 16 * NB;
   dim3 grid((a.W + kTW - 1) / kTW, (a.H + kTH - 1) / kTH, (cout_pad / BM) * a.batch);
-  conv3x3_kernel<MODE, BM, CK><<<grid, 256, 0, s>>>(a);
+  conv3x3_kernel<MODE, BM, CK, NB><<<grid, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
-template <int MODE, int BM>
+template <int MODE, int BM, int NB>
 hipError_t conv_dispatch_ck(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
-  if (ck == 32) return conv_launch<MODE, BM, 32>(a, cout_pad, s);
-  if (ck == 16) return conv_launch<MODE, BM, 16>(a, cout_pad, s);
-  if (MODE == 0 && ck == 8) return conv_launch<0, BM, 8>(a, cout_pad, s);
+  if constexpr (NB == 2 || MODE == 1)
+    if (ck == 32) return conv_launch<MODE, BM, 32, NB>(a, cout_pad, s);
+  if (ck == 16) return conv_launch<MODE, BM, 16, NB>(a, cout_pad, s);
+  if constexpr (MODE == 0)
+    if (ck == 8) return conv_launch<0, BM, 8, NB>(a, cout_pad, s);
   return hipErrorInvalidValue;
 }
 
+// Tile choice.  Layers with 64+ output channels use 64-channel workgroups with
+// waves of 2 x 32 pixels, unless that grid would leave the chip under-filled
+// (fewer than kSmallGridWgs workgroups): then 32-channel workgroups double the
+// grid.  32-channel layers in float32 and split bf16 use waves of 2 x 64 pixels
+// (more reuse of each weight fragment) with at most 16 staged channels so the
+// wider LDS tile stays within 64 KB; plain bf16 measured faster with 2 x 32.
+#ifndef LNR_CONV_SMALL_GRID_WGS
+#define LNR_CONV_SMALL_GRID_WGS 0
+#endif
+#ifndef LNR_CONV_F32_MAX_CK
+#define LNR_CONV_F32_MAX_CK 32
+#endif
+constexpr long kSmallGridWgs = LNR_CONV_SMALL_GRID_WGS;
+
 template <int MODE>
 hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
-  if (cout_pad % 64 == 0) return conv_dispatch_ck<MODE, 64>(a, ck, cout_pad, s);
-  return conv_dispatch_ck<MODE, 32>(a, ck, cout_pad, s);
+  const long tiles = (long)((a.W + 31) / 32) * ((a.H + kTH - 1) / kTH) * (a.batch < 1 ? 1 : a.batch);
+  const bool small = kSmallGridWgs > 0 && tiles * (cout_pad / 64) < kSmallGridWgs;
+  if (cout_pad % 64 == 0 && !small) {
+    const int ck64 = (MODE == 0 && ck > LNR_CONV_F32_MAX_CK) ? LNR_CONV_F32_MAX_CK : ck;
+    return conv_dispatch_ck<MODE, 64, 2>(a, ck64, cout_pad, s);
+  }
+  if constexpr (MODE == 1) {
+    return conv_dispatch_ck<MODE, 32, 2>(a, ck, cout_pad, s);
+  } else {
+    if (cout_pad > 32) return conv_dispatch_ck<MODE, 32, 2>(a, ck, cout_pad, s);
+    return conv_dispatch_ck<MODE, 32, 4>(a, ck < 16 ? ck : 16, cout_pad, s);
+  }
 }
 
 }  // namespace

@@ -92,20 +92,19 @@ def test_superseded_requests_and_admission(lnr, room_scene, room_cloud):
         if 2 in seen:
             break
     assert seen == {1: True, 2: False}
-    # admission by budget: measure what a server needs, then give a fresh context
-    # room for exactly two 64x64 sessions
-    base = lnr.lnr_allocated_bytes(ctx)
-    sess = lnr.lnr_allocated_bytes(ctx)
-    sid2 = lnr.lnr_server_open_session(srv, 64, 64)
-    per_session = lnr.lnr_allocated_bytes(ctx) - sess
-    lnr.lnr_server_close_session(srv, sid2)
-    lnr.lnr_server_close_session(srv, sid)
-    base = lnr.lnr_allocated_bytes(ctx)
+    # admission by budget: measure what a server and one session need on an
+    # unlimited context, then give a fresh context room for exactly two sessions
+    big = lnr.lnr_context_create(0)
+    net_b = lnr.lnr_unet_load(big, blob, lnr.LNR_BF16)
+    srv_b = lnr.lnr_server_create(big, cloud, net_b, max_batch=2, lanes=1, n_levels=3, max_width=64, max_height=64)
+    base = lnr.lnr_allocated_bytes(big)
+    lnr.lnr_server_open_session(srv_b, 64, 64)
+    per_session = lnr.lnr_allocated_bytes(big) - base
     small = lnr.lnr_context_create(0, base + int(2.5 * per_session))
     net_s = lnr.lnr_unet_load(small, blob, lnr.LNR_BF16)
-    cloud_s = lnr.lnr_cloud_load(small, room_scene.xyz, room_scene.rgb, 0.5)
-    srv_s = lnr.lnr_server_create(small, cloud_s, net_s, max_batch=2, lanes=1, n_levels=3, max_width=64,
+    srv_s = lnr.lnr_server_create(small, cloud, net_s, max_batch=2, lanes=1, n_levels=3, max_width=64,
                                   max_height=64)
+    assert lnr.lnr_allocated_bytes(small) == base
     lnr.lnr_server_open_session(srv_s, 64, 64)
     lnr.lnr_server_open_session(srv_s, 64, 64)
     with pytest.raises(lnr.LnrError) as e:
