@@ -146,28 +146,40 @@ def sampled_error(fd, fr, blob, outs, H, W):
     return res
 
 
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_conv_dec0a_multiroom_1080p.json")
-UNET_SRC = os.path.join(ROOT, "paper_2502_11618_amd", "csrc", "unet.hip")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_unet_fp32_multiroom_1080p.json")
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2502_11618_amd", "csrc", f) for f in ("unet.hip", "api.cpp")]
 
 
-def _sha(path):
+def _sources_sha():
     import hashlib
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for path in TRAFFIC_SOURCES:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
 
 
 def summarize_counters(args):
-    """Per-kernel HBM bytes from rocprofv3 --pmc csv files, each counter scaled by
-    what it reads for a plain 1 GiB device copy; writes the dominant kernel's
-    figures (the float32 dec0a convolution: the 2nd of the three level-0
-    conv3x3_kernel<0, 32, 32> dispatches of each frame) next to the source hash."""
+    """Per-kernel HBM bytes from rocprofv3 --pmc csv files of a float32 frames
+    run, each counter scaled by what it reads for a plain 1 GiB device copy.
+    Convolutions are named by their place in the frame (the n-th conv3x3
+    dispatch after each pack dispatch is the n-th layer of conv_shapes), so the
+    figures stay tied to layers whatever template a layer dispatches to.
+    Writes every layer's figures next to the hash of the sources that decide
+    them."""
     import collections
     import csv
 
+    widths = (32, 64, 128, 256)
+    layer_names = [n for (n, *_rest) in conv_shapes(widths, 1080, 1920, 8)]
+
     def rows(path):
-        return list(csv.DictReader(open(path)))
+        return sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
 
     def mean(v):
         return sum(v) / len(v)
+
+    def short(name):
+        return name.replace("lnr::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
 
     gib_kib = (1 << 30) / 1024.0
     f_fac = gib_kib / mean([float(r["Counter_Value"]) for r in rows(args.copy_fetch_csv)
@@ -175,36 +187,46 @@ def summarize_counters(args):
     w_fac = gib_kib / mean([float(r["Counter_Value"]) for r in rows(args.copy_write_csv)
                             if "copyBuffer" in r["Kernel_Name"]])
     per = collections.OrderedDict()
+    kname = {}
     for path, key, fac in ((args.fetch_csv, "fetch", f_fac), (args.write_csv, "write", w_fac)):
+        conv_i = None
         for r in rows(path):
-            name = r["Kernel_Name"].replace("lnr::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+            name = short(r["Kernel_Name"])
+            if name.startswith("pack_kernel"):
+                conv_i = 0
+            elif name.startswith("conv3x3") and conv_i is not None and conv_i < len(layer_names):
+                kname[layer_names[conv_i]] = name
+                name = layer_names[conv_i]
+                conv_i += 1
             per.setdefault(name, {"fetch": [], "write": []})[key].append(float(r["Counter_Value"]) * fac * 1024)
     print(f"counter scale factors from a 1 GiB copy: FETCH_SIZE x{f_fac:.4f}, WRITE_SIZE x{w_fac:.4f}")
-    print(f"{'kernel':40s} {'dispatches':>10s} {'fetch MB':>10s} {'write MB':>10s}")
+    print(f"{'kernel':36s} {'template':34s} {'dispatches':>10s} {'fetch MB':>10s} {'write MB':>10s}")
+    layers = {}
     for name, d in per.items():
-        if d["fetch"]:
-            print(f"{name:40s} {len(d['fetch']):10d} {mean(d['fetch']) / 1e6:10.2f} "
-                  f"{(mean(d['write']) if d['write'] else 0) / 1e6:10.2f}")
-    conv = per["conv3x3_kernel<0, 32, 32>"]
-    fetch = mean(conv["fetch"][1::3])
-    write = mean(conv["write"][1::3])
-    out = {"kernel": "conv/dec0a", "fetch_bytes": fetch, "write_bytes": write,
-           "fetch_scale": f_fac, "write_scale": w_fac, "unet_hip_sha256": _sha(UNET_SRC)}
-    with open(TRAFFIC_JSON, "w") as f:
-        json.dump(out, f, indent=1)
-    print(f"dec0a: fetch {fetch / 1e6:.1f} MB, write {write / 1e6:.1f} MB per launch -> {TRAFFIC_JSON}")
+        if not d["fetch"]:
+            continue
+        f, w = mean(d["fetch"]), (mean(d["write"]) if d["write"] else 0.0)
+        print(f"{name:36s} {kname.get(name, ''):34s} {len(d['fetch']):10d} {f / 1e6:10.2f} {w / 1e6:10.2f}")
+        if name.startswith("conv/"):
+            layers[name] = {"template": kname[name], "fetch_bytes": f, "write_bytes": w}
+    out = {"workload": "multiroom-20M-pts-1920x1080-orbit120, float32 U-Net 32/64/128/256", "layers": layers,
+           "fetch_scale": f_fac, "write_scale": w_fac, "sources_sha256": _sources_sha()}
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"per-layer HBM bytes -> {TRAFFIC_JSON}")
 
 
 def recorded_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None
-    when it was taken for another kernel or the kernel source changed since."""
+    """HBM bytes per launch of the float32 layer `kernel` from the committed
+    counter summary, or None when the sources that decide it changed since."""
     try:
         t = json.load(open(TRAFFIC_JSON))
     except (OSError, ValueError):
         return None
-    if t.get("kernel") != kernel or t.get("unet_hip_sha256") != _sha(UNET_SRC):
+    if t.get("sources_sha256") != _sources_sha() or kernel not in t.get("layers", {}):
         return None
-    return t["fetch_bytes"] + t["write_bytes"]
+    lay = t["layers"][kernel]
+    return lay["fetch_bytes"] + lay["write_bytes"]
 
 
 def serve_bench(L, scene, cloud, blob, seconds, n_sessions=64, seed=0, budget=32 << 30, max_batch=8, lanes=2):

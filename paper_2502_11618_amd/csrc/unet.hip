@@ -319,6 +319,167 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   }
 }
 
+// bfloat16 3x3 convolution with row reuse.  Each wave owns R output rows of a
+// 32-pixel-wide column strip and BM output channels.  For one horizontal tap
+// offset dx and one 16-channel group it reads the R + 2 input-row fragments it
+// needs once and feeds each of them to the up-to-three vertical taps that use
+// it, so the activation operand is read from LDS (R + 2) times per 3R MFMAs
+// instead of 3R times.  N block = 32 consecutive pixels of one row; the
+// accumulator layout, pooling and head epilogues follow the generic kernel
+// (the 2x2 pool partner is the next row's accumulator of the same lane).
+template <int BM, int CK, int R>
+__global__ __launch_bounds__(256) void conv3x3_rows_bf16_kernel(ConvArgs a) {
+  constexpr int S = CK + 8;               // bf16 elements per staged pixel
+  constexpr int MB = BM / 32;
+  constexpr int TH = 4 * R, TW = 32;       // output tile
+  constexpr int LW = TW + 2, LPix = (TH + 2) * LW;
+  __shared__ __attribute__((aligned(16))) uint16_t s_in[LPix * S];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = lane & 31, h = lane >> 5;
+  const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
+  const int nzc = gridDim.z / a.batch;
+  const int bimg = blockIdx.z / nzc;
+  const int co0 = (blockIdx.z - bimg * nzc) * BM;
+  const int H = a.H, W = a.W;
+  const int Cin = a.C0 + a.C1;
+  const uint16_t *in0 = static_cast<const uint16_t *>(a.in0) + (size_t)bimg * a.in0_bs;
+  const uint16_t *in1 = a.in1 ? static_cast<const uint16_t *>(a.in1) + (size_t)bimg * a.in1_bs : nullptr;
+  uint16_t *out = a.out ? static_cast<uint16_t *>(a.out) + (size_t)bimg * a.out_bs : nullptr;
+  uint16_t *out_pool = a.out_pool ? static_cast<uint16_t *>(a.out_pool) + (size_t)bimg * a.pool_bs : nullptr;
+  float *head_out = a.head_outs ? a.head_outs[bimg] : (a.head_out ? a.head_out + (size_t)bimg * 3 * H * W : nullptr);
+  const uint16_t *wp = static_cast<const uint16_t *>(a.w);
+
+  floatx16 acc[MB][R];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[mb][r][q] = 0.f;
+
+  const int row0 = wv * R;  // first output row of this wave within the tile
+  for (int ci = 0; ci < Cin; ci += CK) {
+    const bool from0 = ci < a.C0;
+    const int csrc = from0 ? a.C0 : a.C1;
+    const int coff = from0 ? ci : ci - a.C0;
+    const uint16_t *src = from0 ? in0 : in1;
+    constexpr int NV = CK / 8;
+    for (int e = tid; e < LPix * NV; e += 256) {
+      const int pix = e / NV, q = e - pix * NV;
+      const int gy = ty0 - 1 + pix / LW, gx = tx0 - 1 + pix % LW;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+        const size_t gi = from0 ? ((size_t)gy * W + gx) * csrc + coff + q * 8
+                                : ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * csrc + coff + q * 8;
+        v = *reinterpret_cast<const uint4 *>(src + gi);
+      }
+      *reinterpret_cast<uint4 *>(&s_in[pix * S + q * 8]) = v;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int g = 0; g < CK / 16; ++g) {
+#pragma unroll 1
+      for (int dx = 0; dx < 3; ++dx) {
+        uint4 av[MB][3], bv[R + 2];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+            av[mb][dy] = *reinterpret_cast<const uint4 *>(
+                wp + ((size_t)(co0 + mb * 32 + n) * 9 + dy * 3 + dx) * a.cin_pad + ci + g * 16 + 8 * h);
+#pragma unroll
+        for (int i = 0; i < R + 2; ++i)
+          bv[i] = *reinterpret_cast<const uint4 *>(&s_in[((row0 + i) * LW + n + dx) * S + g * 16 + 8 * h]);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+              acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av[mb][dy]), as_bf16x8(bv[r + dy]),
+                                                                   acc[mb][r], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  const int gx = tx0 + n;
+  if (head_out) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int gy = ty0 + row0 + r;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = co0 + mb * 32 + 8 * j + 4 * h + i;
+            if (c < a.cout) {
+              const float v = fmaxf(acc[mb][r][4 * j + i] + a.bias[c], 0.f);
+              s0 = fmaf(a.head_w[c], v, s0);
+              s1 = fmaf(a.head_w[a.cout + c], v, s1);
+              s2 = fmaf(a.head_w[2 * a.cout + c], v, s2);
+            }
+          }
+      s0 += __shfl_xor(s0, 32, 64);
+      s1 += __shfl_xor(s1, 32, 64);
+      s2 += __shfl_xor(s2, 32, 64);
+      if (h == 0 && gy < H && gx < W) {
+        const size_t HW = (size_t)H * W, p = (size_t)gy * W + gx;
+        head_out[p] = s0 + a.head_b[0];
+        head_out[HW + p] = s1 + a.head_b[1];
+        head_out[2 * HW + p] = s2 + a.head_b[2];
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = co0 + mb * 32 + 8 * j + 4 * h;
+      float v[R][4];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[r][i] = fmaxf(acc[mb][r][4 * j + i] + a.bias[c + i], 0.f);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int gy = ty0 + row0 + r;
+        if (gy < H && gx < W && c < a.cout) {
+          uint16_t b16[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) b16[i] = f2bf(v[r][i]);
+          *reinterpret_cast<uint2 *>(out + ((size_t)gy * W + gx) * a.cout + c) =
+              make_uint2(b16[0] | ((uint32_t)b16[1] << 16), b16[2] | ((uint32_t)b16[3] << 16));
+        }
+      }
+      if (out_pool) {
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+          float m[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            m[i] = fmaxf(v[r][i], v[r + 1][i]);
+            m[i] = fmaxf(m[i], __shfl_xor(m[i], 1, 64));
+          }
+          const int gy = ty0 + row0 + r;
+          if ((n & 1) == 0 && gy < H && gx < W && c < a.cout) {
+            uint16_t b16[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) b16[i] = f2bf(m[i]);
+            *reinterpret_cast<uint2 *>(out_pool + ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * a.cout + c) =
+                make_uint2(b16[0] | ((uint32_t)b16[1] << 16), b16[2] | ((uint32_t)b16[3] << 16));
+          }
+        }
+      }
+    }
+  }
+}
+
 // RGBDA -> network input x = (r/255, g/255, b/255, A ? D/16 : 0, A, 0...), cpad channels
 template <int MODE>
 __global__ __launch_bounds__(256) void pack_kernel(const float *__restrict__ depth, const uint32_t *__restrict__ rgba,
@@ -396,21 +557,51 @@ hipError_t conv_dispatch_ck(const ConvArgs &a, int ck, int cout_pad, hipStream_t
 
 // Tile choice.  Layers with 64+ output channels use 64-channel workgroups with
 // waves of 2 x 32 pixels, unless that grid would leave the chip under-filled
-// (fewer than kSmallGridWgs workgroups): then 32-channel workgroups double the
+// (fewer than kSmallGridWgs workgroups per image): then 32-channel workgroups double the
 // grid.  32-channel layers in float32 and split bf16 use waves of 2 x 64 pixels
 // (more reuse of each weight fragment) with at most 16 staged channels so the
 // wider LDS tile stays within 64 KB; plain bf16 measured faster with 2 x 32.
 #ifndef LNR_CONV_SMALL_GRID_WGS
-#define LNR_CONV_SMALL_GRID_WGS 0
+#define LNR_CONV_SMALL_GRID_WGS 768
 #endif
 #ifndef LNR_CONV_F32_MAX_CK
 #define LNR_CONV_F32_MAX_CK 32
 #endif
 constexpr long kSmallGridWgs = LNR_CONV_SMALL_GRID_WGS;
+#ifndef LNR_CONV_BF16_ROW_REUSE
+#define LNR_CONV_BF16_ROW_REUSE 1
+#endif
+constexpr bool kBf16RowReuse = LNR_CONV_BF16_ROW_REUSE != 0;
+
+template <int BM, int CK>
+hipError_t conv_rows_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
+  constexpr int R = 4;
+  dim3 grid((a.W + 31) / 32, (a.H + 4 * R - 1) / (4 * R), (cout_pad / BM) * a.batch);
+  conv3x3_rows_bf16_kernel<BM, CK, R><<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int BM>
+hipError_t conv_rows_dispatch_ck(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
+  if (ck == 32) return conv_rows_launch<BM, 32>(a, cout_pad, s);
+  if (ck == 16) return conv_rows_launch<BM, 16>(a, cout_pad, s);
+  return hipErrorInvalidValue;
+}
 
 template <int MODE>
 hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
-  const long tiles = (long)((a.W + 31) / 32) * ((a.H + kTH - 1) / kTH) * (a.batch < 1 ? 1 : a.batch);
+  if constexpr (MODE == 1) {
+    // row reuse measured faster at 128 output channels and 270x480 pixels
+    // (510 workgroups), slower at 256 channels on 135x240 (288 workgroups)
+    // and mixed at 32 and 64 channels: keep it to wide layers with enough
+    // 32x16 tiles to occupy the chip.  Like the small-grid switch below, the
+    // choice looks at one image only, so a frame's output does not depend on
+    // the batch it was served in.
+    const long rows_wgs = (long)((a.W + 31) / 32) * ((a.H + 15) / 16) * (cout_pad / 64);
+    if (kBf16RowReuse && cout_pad >= 128 && cout_pad % 64 == 0 && rows_wgs >= 384)
+      return conv_rows_dispatch_ck<64>(a, ck, cout_pad, s);
+  }
+  const long tiles = (long)((a.W + 31) / 32) * ((a.H + kTH - 1) / kTH);
   const bool small = kSmallGridWgs > 0 && tiles * (cout_pad / 64) < kSmallGridWgs;
   if (cout_pad % 64 == 0 && !small) {
     const int ck64 = (MODE == 0 && ck > LNR_CONV_F32_MAX_CK) ? LNR_CONV_F32_MAX_CK : ck;

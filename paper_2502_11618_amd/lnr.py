@@ -237,6 +237,17 @@ def lnr_context_create(hip_device: int = 0, hbm_budget_bytes: int = 0) -> Contex
     return Context(h.value)
 
 
+def lnr_context_destroy(ctx: Context) -> None:
+    """Frees the context and its scratch.  Clouds, networks and servers
+    created through it must be destroyed first."""
+    ctx.__del__()
+
+
+def lnr_last_error(ctx: Optional[Context]) -> str:
+    msg = _lib.lnr_last_error(ctx.handle if ctx is not None else None)
+    return msg.decode() if msg else ""
+
+
 def lnr_allocated_bytes(ctx: Context) -> int:
     return int(_lib.lnr_allocated_bytes(ctx.handle))
 
@@ -250,6 +261,10 @@ def lnr_cloud_load(ctx: Context, xyz: np.ndarray, rgb: np.ndarray, cell_size: fl
     _check(_lib.lnr_cloud_load(ctx.handle, xyz.ctypes.data, rgb.ctypes.data, xyz.shape[0], float(cell_size),
                                ctypes.byref(h)), ctx.handle)
     return Cloud(ctx, h.value)
+
+
+def lnr_cloud_destroy(cloud: Cloud) -> None:
+    cloud.__del__()
 
 
 def lnr_cloud_info(cloud: Cloud):
@@ -317,6 +332,10 @@ def lnr_unet_load(ctx: Context, blob: bytes, precision: int = LNR_FP32) -> UNet:
     return UNet(ctx, h.value, precision, widths)
 
 
+def lnr_unet_destroy(unet: UNet) -> None:
+    unet.__del__()
+
+
 def lnr_reconstruct(ctx: Context, unet: UNet, image: Image, rgb_out, stream=None) -> None:
     img = image.struct()
     _check(_lib.lnr_reconstruct(ctx.handle, unet.handle, ctypes.byref(img), rgb_out.data_ptr(), _stream(stream)),
@@ -364,6 +383,11 @@ def lnr_server_create(ctx: Context, cloud: Cloud, unet: UNet, max_batch: int = 8
     _check(_lib.lnr_server_create(ctx.handle, cloud.handle, unet.handle, ctypes.byref(cfg), ctypes.byref(h)),
            ctx.handle)
     return Server(ctx, h.value, (cloud, unet))
+
+
+def lnr_server_destroy(srv: Server) -> None:
+    """Waits for the server's in-flight batches and frees its lanes and sessions."""
+    srv.__del__()
 
 
 def lnr_server_open_session(srv: Server, width: int, height: int) -> int:

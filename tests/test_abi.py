@@ -52,3 +52,9 @@ def test_context_create_without_a_device():
     with pytest.raises(L.LnrError) as e:
         L.lnr_context_create(0)
     assert e.value.status == L.LNR_E_DEVICE
+
+
+def test_binding_has_every_declared_entry_point():
+    import paper_2502_11618_amd.lnr as B
+    missing = [n for n in _declared() if not callable(getattr(B, n, None))]
+    assert not missing, missing
