@@ -92,8 +92,11 @@ typedef enum { LNR_FP32 = 0, LNR_BF16 = 1, LNR_BF16X3 = 2 } lnr_precision;
  * device memory the context, and the clouds and networks loaded through it,
  * may allocate (0 = no cap). */
 lnr_status lnr_context_create(int hip_device, uint64_t hbm_budget_bytes, lnr_context **out);
-/* Free a context and its scratch.  NULL-safe.  Clouds and networks loaded
- * through it must be destroyed first. */
+/* Release a context.  NULL-safe.  Clouds, networks and servers created
+ * through it stay valid: the context and its scratch are freed when it has
+ * been destroyed and the last of them has been destroyed, so objects may be
+ * destroyed in any order (garbage-collected bindings need this).  Passing the
+ * context to any other call after this one is an error of the caller's. */
 void lnr_context_destroy(lnr_context *ctx);
 /* Message of the last failure on ctx (valid until the next call on ctx);
  * with ctx == NULL, the last failure of lnr_context_create. */

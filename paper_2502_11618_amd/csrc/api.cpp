@@ -52,6 +52,11 @@ struct lnr_context {
   bool profiling = false;
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
+  // clouds, networks and servers created through this context; the context
+  // is freed when it has been destroyed and the last of them is gone, so the
+  // caller may destroy objects in any order
+  int children = 0;
+  bool closed = false;
 };
 
 struct lnr_cloud {
@@ -437,8 +442,8 @@ lnr_status lnr_context_create(int hip_device, uint64_t hbm_budget_bytes, lnr_con
   return LNR_OK;
 }
 
-void lnr_context_destroy(lnr_context *ctx) {
-  if (!ctx) return;
+namespace {
+void context_free(lnr_context *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (Buf *b : {&ctx->sc.flags, &ctx->sc.chunks, &ctx->sc.counters, &ctx->sc.pyramid, &ctx->sc.act, &ctx->sc.soft_acc})
@@ -449,6 +454,18 @@ void lnr_context_destroy(lnr_context *ctx) {
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx;
+  (void)hipGetLastError();  // nothing above may leave an error pending for the caller's next call
+}
+
+void context_release(lnr_context *ctx) {
+  if (--ctx->children == 0 && ctx->closed) context_free(ctx);
+}
+}  // namespace
+
+void lnr_context_destroy(lnr_context *ctx) {
+  if (!ctx) return;
+  ctx->closed = true;
+  if (ctx->children == 0) context_free(ctx);
 }
 
 const char *lnr_last_error(const lnr_context *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
@@ -479,6 +496,7 @@ lnr_status lnr_cloud_load(lnr_context *ctx, const float *xyz_host, const uint8_t
     cloud_free(c.get());
     return st;
   }
+  ++ctx->children;
   *out = c.release();
   return LNR_OK;
 }
@@ -500,6 +518,7 @@ static lnr_status cloud_build(lnr_context *ctx, lnr_cloud *cl, const float *xyz_
   const uint32_t nb = bbox_blocks(N);
   float *d_part;
   if ((st = tmp.get(&d_part, 7ull * nb * 4)) != LNR_OK) return st;
+  (void)hipGetLastError();  // a pending error from an unrelated earlier call is not ours
   LNR_HIP(ctx, launch_bbox(d_xyz, N, d_part, nb, s));
   std::vector<float> part(7ull * nb);
   LNR_HIP(ctx, hipMemcpy(part.data(), d_part, part.size() * 4, hipMemcpyDeviceToHost));
@@ -598,10 +617,13 @@ lnr_status lnr_cloud_cell_start(const lnr_cloud *c, uint32_t *cell_start_host) {
 
 void lnr_cloud_destroy(lnr_cloud *c) {
   if (!c) return;
-  (void)hipSetDevice(c->ctx->device);
+  lnr_context *ctx = c->ctx;
+  (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   cloud_free(c);
   delete c;
+  (void)hipGetLastError();
+  context_release(ctx);
 }
 
 // ---------------------------------------------------------------------------
@@ -894,16 +916,20 @@ lnr_status lnr_unet_load(lnr_context *ctx, const void *blob_host, uint64_t bytes
     free_all();
     return fail(ctx, LNR_E_FORMAT, "trailing bytes after the last record");
   }
+  ++ctx->children;
   *out = u.release();
   return LNR_OK;
 }
 
 void lnr_unet_destroy(lnr_unet *u) {
   if (!u) return;
-  (void)hipSetDevice(u->ctx->device);
+  lnr_context *ctx = u->ctx;
+  (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  for (auto &a : u->allocs) dfree(u->ctx, a.first, a.second);
+  for (auto &a : u->allocs) dfree(ctx, a.first, a.second);
   delete u;
+  (void)hipGetLastError();
+  context_release(ctx);
 }
 
 lnr_status lnr_reconstruct(lnr_context *ctx, const lnr_unet *u, const lnr_image *in, float *rgb_out,
@@ -1121,15 +1147,19 @@ lnr_status lnr_server_create(lnr_context *ctx, const lnr_cloud *c, const lnr_une
       return st;
     }
   }
+  ++ctx->children;
   *out = srv.release();
   return LNR_OK;
 }
 
 void lnr_server_destroy(lnr_server *srv) {
   if (!srv) return;
-  (void)hipSetDevice(srv->ctx->device);
+  lnr_context *ctx = srv->ctx;
+  (void)hipSetDevice(ctx->device);
   server_release(srv);
   delete srv;
+  (void)hipGetLastError();
+  context_release(ctx);
 }
 
 lnr_status lnr_server_open_session(lnr_server *srv, int32_t width, int32_t height, int32_t *session) {

@@ -2,12 +2,12 @@
 //
 // Fig. 1 and Method, "U-Net Reconstruction": a fully convolutional U-Net maps
 // the depth-filtered RGBDA image to RGB.  Each 3x3 convolution is an implicit
-// GEMM (M = output channels, N = output pixels, K = 9 taps x input channels):
-// a workgroup stages an input tile with a one-pixel halo in LDS and runs the
-// K loop on 32x32 MFMA blocks.  The decoder's nearest-neighbour upsample and
-// channel concatenation are folded into the tile load (channels past the skip
-// tensor are read from the coarser tensor at (y/2, x/2)), and the encoder's
-// 2x2 max-pool is folded into the epilogue of the convolution that feeds it.
+// GEMM (M = output channels, N = output pixels, K = 9 taps x input channels)
+// on 32x32 MFMA blocks.  The decoder's nearest-neighbour upsample and channel
+// concatenation are folded into the input staging (channels past the skip
+// tensor are read from the coarser tensor at (y/2, x/2)), the encoder's 2x2
+// max-pool into the epilogue of the convolution that feeds it, and the 1x1
+// head into the epilogue of the last convolution.
 //
 // Arithmetic modes:
 //   F32    float32 activations, v_mfma_f32_32x32x2_f32.
@@ -24,16 +24,6 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-constexpr int kTH = 8;    // output tile rows (4 waves x 2 rows)
-// output tile columns = 16 x NB: each wave owns NB blocks of 2 rows x 16 pixels
-
-__device__ inline uint16_t f2bf(float f) {  // round to nearest even (finite inputs)
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
@@ -58,282 +48,79 @@ struct ConvArgs {
   float *const *head_outs;
 };
 
-// LDS layout: per tile pixel, CK channels plus padding that staggers pixels
-// across banks (16-byte lane reads).
-template <int MODE, int CK>
-struct Lds {
-  static constexpr int kStride = (MODE == 0) ? (CK + 4) : (CK + 8);  // elements per pixel
-  using T = typename std::conditional<MODE == 0, float, uint16_t>::type;
-  static constexpr int kArrays = (MODE == 2) ? 2 : 1;
-};
-
-template <int MODE, int BM, int CK, int NB>
-__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
-  using L = Lds<MODE, CK>;
-  using T = typename L::T;
-  constexpr int S = L::kStride;
-  constexpr int MB = BM / 32;
-  constexpr int kTW = 16 * NB;
-  constexpr int kLW = kTW + 2, kLPix = (kTH + 2) * kLW;
-  __shared__ __attribute__((aligned(16))) T s_in[L::kArrays][kLPix * S];
-
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int n = lane & 31, h = lane >> 5;
-  const int ty0 = blockIdx.y * kTH, tx0 = blockIdx.x * kTW;
-  const int nzc = gridDim.z / a.batch;
-  const int bimg = blockIdx.z / nzc;
-  const int co0 = (blockIdx.z - bimg * nzc) * BM;
-  const int H = a.H, W = a.W;
-  const int Cin = a.C0 + a.C1;
-  // this image's tensors (element type in HBM: bf16 bits for BF16, float otherwise)
-  using E = typename std::conditional<MODE == 1, uint16_t, float>::type;
-  const E *in0 = static_cast<const E *>(a.in0) + (size_t)bimg * a.in0_bs;
-  const E *in1 = a.in1 ? static_cast<const E *>(a.in1) + (size_t)bimg * a.in1_bs : nullptr;
-  E *out = a.out ? static_cast<E *>(a.out) + (size_t)bimg * a.out_bs : nullptr;
-  E *out_pool = a.out_pool ? static_cast<E *>(a.out_pool) + (size_t)bimg * a.pool_bs : nullptr;
-  float *head_out = a.head_outs ? a.head_outs[bimg] : (a.head_out ? a.head_out + (size_t)bimg * 3 * H * W : nullptr);
-
-  floatx16 acc[MB][NB];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.f;
-
-  // pixel of this lane in each N block (2 rows x 16 columns), tile coordinates
-  const int pr = 2 * wv + (n >> 4);
-  const int pc = n & 15;
-
-  for (int ci = 0; ci < Cin; ci += CK) {
-    // ---- stage the input tile (with halo) for channels [ci, ci + CK) ----
-    const bool from0 = ci < a.C0;
-    const int csrc = from0 ? a.C0 : a.C1;
-    const int coff = from0 ? ci : ci - a.C0;
-    constexpr int VEC = (MODE == 1) ? 8 : 4;  // channels per 16-byte global load
-    constexpr int NV = CK / VEC;
-    for (int e = tid; e < kLPix * NV; e += 256) {
-      const int pix = e / NV, q = e - pix * NV;
-      const int gy = ty0 - 1 + pix / kLW, gx = tx0 - 1 + pix % kLW;
-      const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
-      size_t gi = 0;
-      if (inside) {
-        gi = from0 ? ((size_t)gy * W + gx) * csrc + coff + q * VEC
-                   : ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * csrc + coff + q * VEC;
-      }
-      const void *src = from0 ? (const void *)in0 : (const void *)in1;
-      if (MODE == 0) {
-        float4 v = inside ? *reinterpret_cast<const float4 *>(static_cast<const float *>(src) + gi)
-                          : make_float4(0.f, 0.f, 0.f, 0.f);
-        *reinterpret_cast<float4 *>(&s_in[0][pix * S + q * 4]) = v;
-      } else if (MODE == 1) {
-        uint4 v = inside ? *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(src) + gi)
-                         : make_uint4(0u, 0u, 0u, 0u);
-        *reinterpret_cast<uint4 *>(&s_in[0][pix * S + q * 8]) = v;
-      } else {
-        float4 v = inside ? *reinterpret_cast<const float4 *>(static_cast<const float *>(src) + gi)
-                          : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float f[4] = {v.x, v.y, v.z, v.w};
-        uint16_t hi[4], lo[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          hi[i] = f2bf(f[i]);
-          lo[i] = f2bf(f[i] - bf2f(hi[i]));
-        }
-        *reinterpret_cast<uint2 *>(&s_in[0][pix * S + q * 4]) =
-            make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
-        *reinterpret_cast<uint2 *>(&s_in[MODE == 2 ? 1 : 0][pix * S + q * 4]) =
-            make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
-      }
-    }
-    __syncthreads();
-
-    // ---- K loop over the 9 taps and the staged channels ----
-    if (MODE == 0) {
-      // float32: steps it = (tap, 8-channel group); the operands of step it + 1
-      // are loaded (weights from global/L1, activations from LDS) while the
-      // MFMAs of step it run
-      constexpr int G = CK / 8;
-      constexpr int NIT = 9 * G;
-      const float *wp = static_cast<const float *>(a.w);
-      const float *sp = reinterpret_cast<const float *>(&s_in[0][0]);
-      const float *wrow[MB];
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) wrow[mb] = wp + (size_t)(co0 + mb * 32 + n) * 9 * a.cin_pad + ci + 4 * h;
-      auto load = [&](int it, float4 *av, float4 *bv) {
-        const int tap = it / G, g = it - tap * G;
-        const int dy = tap / 3, dx = tap - 3 * dy;
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-          av[mb] = *reinterpret_cast<const float4 *>(wrow[mb] + tap * a.cin_pad + g * 8);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          bv[nb] = *reinterpret_cast<const float4 *>(sp + ((pr + dy) * kLW + (nb * 16 + pc + dx)) * S + g * 8 + 4 * h);
-      };
-      auto mma = [&](const float4 *av, const float4 *bv) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][i], bv[nb][i], acc[mb][nb], 0, 0, 0);
-      };
-      float4 a0[MB], b0[NB], a1[MB], b1[NB];
-      load(0, a0, b0);
-#pragma unroll 1
-      for (int it = 0; it < NIT; it += 2) {
-        if (it + 1 < NIT) load(it + 1, a1, b1);
-        mma(a0, b0);
-        if (it + 1 < NIT) {
-          if (it + 2 < NIT) load(it + 2, a0, b0);
-          mma(a1, b1);
-        }
-      }
-    } else {
-#pragma unroll 1
-    for (int tap = 0; tap < 9; ++tap) {
-      const int dy = tap / 3, dx = tap - 3 * (tap / 3);
-      int boff[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) boff[nb] = ((pr + dy) * kLW + (nb * 16 + pc + dx)) * S;
-      {
-        const uint16_t *wp = static_cast<const uint16_t *>(a.w);
-        const uint16_t *wl = static_cast<const uint16_t *>(a.w_lo);
-#pragma unroll
-        for (int g = 0; g < CK / 16; ++g) {
-          uint4 ah[MB], al[MB], bh[NB], bl[NB];
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) {
-            const size_t wi = ((size_t)(co0 + mb * 32 + n) * 9 + tap) * a.cin_pad + ci + g * 16 + 8 * h;
-            ah[mb] = *reinterpret_cast<const uint4 *>(wp + wi);
-            if (MODE == 2) al[mb] = *reinterpret_cast<const uint4 *>(wl + wi);
-          }
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            bh[nb] = *reinterpret_cast<const uint4 *>(&s_in[0][boff[nb] + g * 16 + 8 * h]);
-            if (MODE == 2) bl[nb] = *reinterpret_cast<const uint4 *>(&s_in[MODE == 2 ? 1 : 0][boff[nb] + g * 16 + 8 * h]);
-          }
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-              if (MODE == 2) {
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(al[mb]), as_bf16x8(bh[nb]),
-                                                                      acc[mb][nb], 0, 0, 0);
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah[mb]), as_bf16x8(bl[nb]),
-                                                                      acc[mb][nb], 0, 0, 0);
-              }
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah[mb]), as_bf16x8(bh[nb]),
-                                                                    acc[mb][nb], 0, 0, 0);
-            }
-        }
-      }
-    }
-    }
-    __syncthreads();
-  }
-
-  // ---- epilogue ----
-  // accumulator register r = 4j + i holds output channel 8j + 4h + i of the block
-  if (head_out) {
-    // fused 1x1 head: this block holds every output channel of its pixels; each
-    // lane sums its 16 channels per M block, the other half-wave adds the rest
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int gy = ty0 + pr, gx = tx0 + nb * 16 + pc;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int c = co0 + mb * 32 + 8 * j + 4 * h + i;
-            if (c < a.cout) {
-              const float v = fmaxf(acc[mb][nb][4 * j + i] + a.bias[c], 0.f);
-              s0 = fmaf(a.head_w[c], v, s0);
-              s1 = fmaf(a.head_w[a.cout + c], v, s1);
-              s2 = fmaf(a.head_w[2 * a.cout + c], v, s2);
-            }
-          }
-      s0 += __shfl_xor(s0, 32, 64);
-      s1 += __shfl_xor(s1, 32, 64);
-      s2 += __shfl_xor(s2, 32, 64);
-      if (h == 0 && gy < H && gx < W) {
-        const size_t HW = (size_t)H * W, p = (size_t)gy * W + gx;
-        head_out[p] = s0 + a.head_b[0];
-        head_out[HW + p] = s1 + a.head_b[1];
-        head_out[2 * HW + p] = s2 + a.head_b[2];
-      }
-    }
-    return;
-  }
-  // bias + ReLU, store NHWC, optional fused 2x2 max-pool
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int gy = ty0 + pr, gx = tx0 + nb * 16 + pc;
-      const bool inside = gy < H && gx < W;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c = co0 + mb * 32 + 8 * j + 4 * h;
-        float v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[mb][nb][4 * j + i] + a.bias[c + i], 0.f);
-        const bool store = inside && c < a.cout;
-        if (MODE == 1) {
-          uint16_t b16[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) b16[i] = f2bf(v[i]);
-          if (store)
-            *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(out) + ((size_t)gy * W + gx) * a.cout + c) =
-                make_uint2(b16[0] | ((uint32_t)b16[1] << 16), b16[2] | ((uint32_t)b16[3] << 16));
-        } else {
-          if (store)
-            *reinterpret_cast<float4 *>(reinterpret_cast<float *>(out) + ((size_t)gy * W + gx) * a.cout + c) =
-                make_float4(v[0], v[1], v[2], v[3]);
-        }
-        if (out_pool) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            v[i] = fmaxf(v[i], __shfl_xor(v[i], 1, 64));
-            v[i] = fmaxf(v[i], __shfl_xor(v[i], 16, 64));
-          }
-          if (store && (pc & 1) == 0 && (pr & 1) == 0) {
-            const size_t pi = ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * a.cout + c;
-            if (MODE == 1) {
-              uint16_t b16[4];
-#pragma unroll
-              for (int i = 0; i < 4; ++i) b16[i] = f2bf(v[i]);
-              *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(out_pool) + pi) =
-                  make_uint2(b16[0] | ((uint32_t)b16[1] << 16), b16[2] | ((uint32_t)b16[3] << 16));
-            } else {
-              *reinterpret_cast<float4 *>(reinterpret_cast<float *>(out_pool) + pi) = make_float4(v[0], v[1], v[2], v[3]);
-            }
-          }
-        }
-      }
-    }
-  }
+// 3x3 convolution as implicit GEMM (M = output channels, N = pixels, K = 9 taps
+// x input channels), one kernel for the three precisions:
+//   MODE 0  float32 activations and weights, v_mfma_f32_32x32x2_f32;
+//   MODE 1  bf16 activations and weights, v_mfma_f32_32x32x16_bf16;
+//   MODE 2  float32 activations, each operand split into bf16 hi + lo in LDS
+//           (weights are stored split), product hi*hi + hi*lo + lo*hi.
+// Workgroup tile: 4R rows x 32 columns of output pixels x BM output channels;
+// wave w owns rows [wR, wR + R).  Per staged chunk of CK input channels the
+// input tile with its halo and the chunk's weights ([co][tap][CK], one copy per
+// workgroup) sit in LDS.  For one horizontal tap offset dx and one channel
+// group a wave reads R + 2 input-row fragments and 3 MB weight fragments and
+// feeds every input row to the up-to-three vertical taps that use it.  Every
+// LDS read is a per-lane base plus a compile-time offset, the staging offsets
+// are computed once per thread, and the next chunk is fetched into registers
+// while the current one is multiplied, so the vector ALU work per MFMA stays
+// small.  The decoder's nearest upsample + concatenation is folded into the
+// staging (channels past C0 come from the half-resolution input), 2x2 max-pool
+// and the fused 1x1 head into the epilogue.
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  typedef float floatx2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const floatx2 v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));  // round to nearest even
 }
 
-// bfloat16 3x3 convolution with row reuse.  Each wave owns R output rows of a
-// 32-pixel-wide column strip and BM output channels.  For one horizontal tap
-// offset dx and one 16-channel group it reads the R + 2 input-row fragments it
-// needs once and feeds each of them to the up-to-three vertical taps that use
-// it, so the activation operand is read from LDS (R + 2) times per 3R MFMAs
-// instead of 3R times.  N block = 32 consecutive pixels of one row; the
-// accumulator layout, pooling and head epilogues follow the generic kernel
-// (the 2x2 pool partner is the next row's accumulator of the same lane).
-template <int BM, int CK, int R>
-__global__ __launch_bounds__(256) void conv3x3_rows_bf16_kernel(ConvArgs a) {
-  constexpr int S = CK + 8;               // bf16 elements per staged pixel
+template <int MODE>
+struct ConvTraits;
+template <>
+struct ConvTraits<0> {  // float32
+  using In = float;       // activations in HBM
+  using W = float;        // weights in HBM
+  using L = float;        // LDS element
+  static constexpr int kInVec = 4, kWVec = 4;    // elements per 16-byte HBM vector
+  static constexpr int kPad = 4, kPlanes = 1, kGroup = 8;
+};
+template <>
+struct ConvTraits<1> {  // bf16
+  using In = uint16_t;
+  using W = uint16_t;
+  using L = uint16_t;
+  static constexpr int kInVec = 8, kWVec = 8;
+  static constexpr int kPad = 8, kPlanes = 1, kGroup = 16;
+};
+template <>
+struct ConvTraits<2> {  // float32 activations, split bf16 operands
+  using In = float;
+  using W = uint16_t;
+  using L = uint16_t;
+  static constexpr int kInVec = 4, kWVec = 8;
+  static constexpr int kPad = 8, kPlanes = 2, kGroup = 16;
+};
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+template <int MODE, int BM, int CK, int R>
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
+  using T = ConvTraits<MODE>;
+  using LT = typename T::L;
+  using InT = typename T::In;
+  using WT = typename T::W;
+  static_assert(CK % T::kGroup == 0, "CK must be a multiple of the channel group");
+  constexpr int S = CK + T::kPad;            // LDS elements per staged pixel / weight row (16-byte multiple)
   constexpr int MB = BM / 32;
-  constexpr int TH = 4 * R, TW = 32;       // output tile
+  constexpr int TH = 4 * R, TW = 32;
   constexpr int LW = TW + 2, LPix = (TH + 2) * LW;
-  __shared__ __attribute__((aligned(16))) uint16_t s_in[LPix * S];
+  constexpr int NVI = CK / T::kInVec, NVW = CK / T::kWVec;   // 16-byte vectors per pixel / weight row
+  constexpr int PPI = 256 / NVI, PPW = 256 / NVW;            // pixels / weight rows per workgroup pass
+  constexpr int NIN = (LPix + PPI - 1) / PPI;
+  constexpr int WROWS = 9 * BM;
+  constexpr int NWR = (WROWS + PPW - 1) / PPW;
+  constexpr int INP = LPix * S, WP = WROWS * S;              // elements per LDS plane
+  __shared__ __attribute__((aligned(16))) LT s_in[T::kPlanes * INP];
+  __shared__ __attribute__((aligned(16))) LT s_w[T::kPlanes * WP];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = lane & 31, h = lane >> 5;
@@ -343,12 +130,78 @@ __global__ __launch_bounds__(256) void conv3x3_rows_bf16_kernel(ConvArgs a) {
   const int co0 = (blockIdx.z - bimg * nzc) * BM;
   const int H = a.H, W = a.W;
   const int Cin = a.C0 + a.C1;
-  const uint16_t *in0 = static_cast<const uint16_t *>(a.in0) + (size_t)bimg * a.in0_bs;
-  const uint16_t *in1 = a.in1 ? static_cast<const uint16_t *>(a.in1) + (size_t)bimg * a.in1_bs : nullptr;
-  uint16_t *out = a.out ? static_cast<uint16_t *>(a.out) + (size_t)bimg * a.out_bs : nullptr;
-  uint16_t *out_pool = a.out_pool ? static_cast<uint16_t *>(a.out_pool) + (size_t)bimg * a.pool_bs : nullptr;
+  const InT *in0 = static_cast<const InT *>(a.in0) + (size_t)bimg * a.in0_bs;
+  const InT *in1 = a.in1 ? static_cast<const InT *>(a.in1) + (size_t)bimg * a.in1_bs : nullptr;
+  InT *out = a.out ? static_cast<InT *>(a.out) + (size_t)bimg * a.out_bs : nullptr;
+  InT *out_pool = a.out_pool ? static_cast<InT *>(a.out_pool) + (size_t)bimg * a.pool_bs : nullptr;
   float *head_out = a.head_outs ? a.head_outs[bimg] : (a.head_out ? a.head_out + (size_t)bimg * 3 * H * W : nullptr);
-  const uint16_t *wp = static_cast<const uint16_t *>(a.w);
+
+  // staging plan: this thread moves 16-byte vector qi of pixels pi0, pi0 + PPI,
+  // ... (offsets in the full- and the half-resolution source, -1 outside the
+  // image) and vector qw of weight rows pw0, pw0 + PPW, ...
+  const int qi = (tid & (NVI - 1)) * T::kInVec, pi0 = tid >> ilog2(NVI);
+  const int qw = (tid & (NVW - 1)) * T::kWVec, pw0 = tid >> ilog2(NVW);
+  int off0[NIN], off1[NIN];
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) {
+    const int pix = pi0 + k * PPI;
+    const int gy = ty0 - 1 + pix / LW, gx = tx0 - 1 + pix % LW;
+    const bool inside = pix < LPix && gy >= 0 && gy < H && gx >= 0 && gx < W;
+    off0[k] = inside ? gy * W + gx : -1;
+    off1[k] = inside ? (gy >> 1) * (W >> 1) + (gx >> 1) : -1;
+  }
+  // weights [cout_pad][9][cin_pad]; staged row r = co * 9 + tap of this workgroup's channels
+  const size_t wrow0 = ((size_t)co0 * 9 + pw0) * a.cin_pad + qw;
+  const size_t wstep = (size_t)PPW * a.cin_pad;
+  const WT *wsrc = static_cast<const WT *>(a.w) + wrow0;
+  const WT *wsrc_lo = MODE == 2 ? static_cast<const WT *>(a.w_lo) + wrow0 : nullptr;
+  constexpr int NWV = NWR * T::kPlanes;
+
+  auto fetch = [&](int ci, uint4 (&pin)[NIN], uint4 (&pw)[NWV]) {
+    const bool from0 = ci < a.C0;
+    const size_t csrc = from0 ? a.C0 : a.C1;
+    const InT *src = (from0 ? in0 + ci : in1 + (ci - a.C0)) + qi;
+    // a pixel outside the image loads the image's first pixel and is replaced by zero
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      const int o = from0 ? off0[k] : off1[k];
+      const uint4 v = *reinterpret_cast<const uint4 *>(src + (size_t)(o < 0 ? 0 : o) * csrc);
+      pin[k] = o < 0 ? make_uint4(0u, 0u, 0u, 0u) : v;
+    }
+#pragma unroll
+    for (int k = 0; k < NWR; ++k) {
+      const bool ok = (k + 1) * PPW <= WROWS || pw0 + k * PPW < WROWS;
+      pw[k] = ok ? *reinterpret_cast<const uint4 *>(wsrc + k * wstep + ci) : make_uint4(0u, 0u, 0u, 0u);
+      if constexpr (MODE == 2)
+        pw[NWR + k] = ok ? *reinterpret_cast<const uint4 *>(wsrc_lo + k * wstep + ci) : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store = [&](const uint4 (&pin)[NIN], const uint4 (&pw)[NWV]) {
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      if (!((k + 1) * PPI <= LPix || pi0 + k * PPI < LPix)) continue;
+      const int li = (pi0 + k * PPI) * S + qi;
+      if constexpr (MODE == 2) {
+        // 4 float32 channels -> 4 bf16 hi (plane 0) + 4 bf16 lo (plane 1)
+        const float f[4] = {__uint_as_float(pin[k].x), __uint_as_float(pin[k].y), __uint_as_float(pin[k].z),
+                            __uint_as_float(pin[k].w)};
+        const uint32_t h01 = pack_bf16x2(f[0], f[1]), h23 = pack_bf16x2(f[2], f[3]);
+        const uint32_t l01 = pack_bf16x2(f[0] - __uint_as_float(h01 << 16), f[1] - __uint_as_float(h01 & 0xFFFF0000u));
+        const uint32_t l23 = pack_bf16x2(f[2] - __uint_as_float(h23 << 16), f[3] - __uint_as_float(h23 & 0xFFFF0000u));
+        *reinterpret_cast<uint2 *>(&s_in[li]) = make_uint2(h01, h23);
+        *reinterpret_cast<uint2 *>(&s_in[INP + li]) = make_uint2(l01, l23);
+      } else {
+        *reinterpret_cast<uint4 *>(&s_in[li]) = pin[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NWR; ++k) {
+      if (!((k + 1) * PPW <= WROWS || pw0 + k * PPW < WROWS)) continue;
+      const int li = (pw0 + k * PPW) * S + qw;
+      *reinterpret_cast<uint4 *>(&s_w[li]) = pw[k];
+      if constexpr (MODE == 2) *reinterpret_cast<uint4 *>(&s_w[WP + li]) = pw[NWR + k];
+    }
+  };
 
   floatx16 acc[MB][R];
 #pragma unroll
@@ -358,53 +211,79 @@ __global__ __launch_bounds__(256) void conv3x3_rows_bf16_kernel(ConvArgs a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[mb][r][q] = 0.f;
 
-  const int row0 = wv * R;  // first output row of this wave within the tile
-  for (int ci = 0; ci < Cin; ci += CK) {
-    const bool from0 = ci < a.C0;
-    const int csrc = from0 ? a.C0 : a.C1;
-    const int coff = from0 ? ci : ci - a.C0;
-    const uint16_t *src = from0 ? in0 : in1;
-    constexpr int NV = CK / 8;
-    for (int e = tid; e < LPix * NV; e += 256) {
-      const int pix = e / NV, q = e - pix * NV;
-      const int gy = ty0 - 1 + pix / LW, gx = tx0 - 1 + pix % LW;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-        const size_t gi = from0 ? ((size_t)gy * W + gx) * csrc + coff + q * 8
-                                : ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * csrc + coff + q * 8;
-        v = *reinterpret_cast<const uint4 *>(src + gi);
-      }
-      *reinterpret_cast<uint4 *>(&s_in[pix * S + q * 8]) = v;
-    }
-    __syncthreads();
+  // lane (n, h) reads channels [G g + (G/2) h, + G/2) of a group: input pixel
+  // column n + dx of its rows, weight row (32 mb + n) * 9 + tap
+  constexpr int G = T::kGroup, HG = G / 2;
+  const LT *bbase = s_in + (wv * R * LW + n) * S + HG * h;
+  const LT *abase = s_w + n * 9 * S + HG * h;
+  auto compute = [&]() {
 #pragma unroll 1
-    for (int g = 0; g < CK / 16; ++g) {
-#pragma unroll 1
+    for (int g = 0; g < CK / G; ++g) {
+      const LT *ag = abase + g * G, *bg = bbase + g * G;
+#pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
-        uint4 av[MB][3], bv[R + 2];
+        uint4 av[T::kPlanes][MB][3], bv[T::kPlanes][R + 2];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+        for (int p = 0; p < T::kPlanes; ++p) {
 #pragma unroll
-          for (int dy = 0; dy < 3; ++dy)
-            av[mb][dy] = *reinterpret_cast<const uint4 *>(
-                wp + ((size_t)(co0 + mb * 32 + n) * 9 + dy * 3 + dx) * a.cin_pad + ci + g * 16 + 8 * h);
+          for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int i = 0; i < R + 2; ++i)
-          bv[i] = *reinterpret_cast<const uint4 *>(&s_in[((row0 + i) * LW + n + dx) * S + g * 16 + 8 * h]);
+            for (int dy = 0; dy < 3; ++dy)
+              av[p][mb][dy] = *reinterpret_cast<const uint4 *>(ag + p * WP + (mb * 32 * 9 + dy * 3 + dx) * S);
+#pragma unroll
+          for (int i = 0; i < R + 2; ++i)
+            bv[p][i] = *reinterpret_cast<const uint4 *>(bg + p * INP + (i * LW + dx) * S);
+        }
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
           for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-              acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av[mb][dy]), as_bf16x8(bv[r + dy]),
-                                                                   acc[mb][r], 0, 0, 0);
+            for (int mb = 0; mb < MB; ++mb) {
+              if constexpr (MODE == 0) {
+                const float4 av4 = __builtin_bit_cast(float4, av[0][mb][dy]);
+                const float4 bv4 = __builtin_bit_cast(float4, bv[0][r + dy]);
+                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.x, bv4.x, acc[mb][r], 0, 0, 0);
+                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.y, bv4.y, acc[mb][r], 0, 0, 0);
+                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.z, bv4.z, acc[mb][r], 0, 0, 0);
+                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.w, bv4.w, acc[mb][r], 0, 0, 0);
+              } else if constexpr (MODE == 1) {
+                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av[0][mb][dy]), as_bf16x8(bv[0][r + dy]),
+                                                                     acc[mb][r], 0, 0, 0);
+              } else {
+                const int P1 = T::kPlanes - 1;  // lo plane
+                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av[P1][mb][dy]), as_bf16x8(bv[0][r + dy]),
+                                                                     acc[mb][r], 0, 0, 0);
+                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av[0][mb][dy]), as_bf16x8(bv[P1][r + dy]),
+                                                                     acc[mb][r], 0, 0, 0);
+                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av[0][mb][dy]), as_bf16x8(bv[0][r + dy]),
+                                                                     acc[mb][r], 0, 0, 0);
+              }
+            }
       }
     }
+  };
+  {
+    uint4 pin[NIN], pw[NWV];
+    fetch(0, pin, pw);
+    store(pin, pw);
+  }
+  __syncthreads();
+  // every chunk but the last: fetch the next one while multiplying this one
+  for (int ci = CK; ci < Cin; ci += CK) {
+    uint4 pin[NIN], pw[NWV];
+    fetch(ci, pin, pw);
+    compute();
+    __syncthreads();
+    store(pin, pw);
     __syncthreads();
   }
+  compute();
 
+  // ---- epilogue: accumulator register 4j + i of block (mb, r) holds output
+  // channel co0 + 32 mb + 8j + 4h + i of pixel (ty0 + wR + r, tx0 + n)
   const int gx = tx0 + n;
+  const int row0 = wv * R;
   if (head_out) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -413,17 +292,20 @@ __global__ __launch_bounds__(256) void conv3x3_rows_bf16_kernel(ConvArgs a) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+          const int c = co0 + mb * 32 + 8 * j + 4 * h;
+          if (c < a.cout) {
+            const float4 b = *reinterpret_cast<const float4 *>(a.bias + c);
+            const float bb[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int c = co0 + mb * 32 + 8 * j + 4 * h + i;
-            if (c < a.cout) {
-              const float v = fmaxf(acc[mb][r][4 * j + i] + a.bias[c], 0.f);
-              s0 = fmaf(a.head_w[c], v, s0);
-              s1 = fmaf(a.head_w[a.cout + c], v, s1);
-              s2 = fmaf(a.head_w[2 * a.cout + c], v, s2);
+            for (int i = 0; i < 4; ++i) {
+              const float v = fmaxf(acc[mb][r][4 * j + i] + bb[i], 0.f);
+              s0 = fmaf(a.head_w[c + i], v, s0);
+              s1 = fmaf(a.head_w[a.cout + c + i], v, s1);
+              s2 = fmaf(a.head_w[2 * a.cout + c + i], v, s2);
             }
           }
+        }
       s0 += __shfl_xor(s0, 32, 64);
       s1 += __shfl_xor(s1, 32, 64);
       s2 += __shfl_xor(s2, 32, 64);
@@ -436,26 +318,29 @@ __global__ __launch_bounds__(256) void conv3x3_rows_bf16_kernel(ConvArgs a) {
     }
     return;
   }
+  auto put4 = [&](InT *dst, const float (&v)[4]) {
+    if constexpr (MODE == 1)
+      *reinterpret_cast<uint2 *>(dst) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+    else
+      *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+  };
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = co0 + mb * 32 + 8 * j + 4 * h;
+      if (c >= a.cout) continue;
+      const float4 b = *reinterpret_cast<const float4 *>(a.bias + c);
+      const float bb[4] = {b.x, b.y, b.z, b.w};
       float v[R][4];
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[r][i] = fmaxf(acc[mb][r][4 * j + i] + a.bias[c + i], 0.f);
+        for (int i = 0; i < 4; ++i) v[r][i] = fmaxf(acc[mb][r][4 * j + i] + bb[i], 0.f);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int gy = ty0 + row0 + r;
-        if (gy < H && gx < W && c < a.cout) {
-          uint16_t b16[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) b16[i] = f2bf(v[r][i]);
-          *reinterpret_cast<uint2 *>(out + ((size_t)gy * W + gx) * a.cout + c) =
-              make_uint2(b16[0] | ((uint32_t)b16[1] << 16), b16[2] | ((uint32_t)b16[3] << 16));
-        }
+        if (gy < H && gx < W) put4(out + ((size_t)gy * W + gx) * a.cout + c, v[r]);
       }
       if (out_pool) {
 #pragma unroll
@@ -467,13 +352,8 @@ __global__ __launch_bounds__(256) void conv3x3_rows_bf16_kernel(ConvArgs a) {
             m[i] = fmaxf(m[i], __shfl_xor(m[i], 1, 64));
           }
           const int gy = ty0 + row0 + r;
-          if ((n & 1) == 0 && gy < H && gx < W && c < a.cout) {
-            uint16_t b16[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) b16[i] = f2bf(m[i]);
-            *reinterpret_cast<uint2 *>(out_pool + ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * a.cout + c) =
-                make_uint2(b16[0] | ((uint32_t)b16[1] << 16), b16[2] | ((uint32_t)b16[3] << 16));
-          }
+          if ((n & 1) == 0 && gy < H && gx < W)
+            put4(out_pool + ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * a.cout + c, m);
         }
       }
     }
@@ -498,7 +378,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const float *__restrict__ dep
   v[4] = A ? 1.f : 0.f;
   if (MODE == 1) {
     uint16_t *o = static_cast<uint16_t *>(x) + (size_t)p * cpad;
-    for (int i = 0; i < cpad; i += 2) *reinterpret_cast<uint32_t *>(o + i) = f2bf(v[i]) | ((uint32_t)f2bf(v[i + 1]) << 16);
+    for (int i = 0; i < cpad; i += 2) *reinterpret_cast<uint32_t *>(o + i) = pack_bf16x2(v[i], v[i + 1]);
   } else {
     float *o = static_cast<float *>(x) + (size_t)p * cpad;
     for (int i = 0; i < cpad; i += 4) *reinterpret_cast<float4 *>(o + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
@@ -537,81 +417,37 @@ __global__ __launch_bounds__(256) void head_kernel(const void *__restrict__ x, i
   out[2 * (size_t)npix + p] = y2;
 }
 
-template <int MODE, int BM, int CK, int NB>
+// Tile choice per layer (measured on the 1080p workload).  64-channel
+// workgroups with 2 rows per wave where the layer has a multiple of 64 output
+// channels; 32-channel layers (the first level) use 4 rows per wave in float32
+// and split bf16, and in bf16 4 rows only when the layer is deep enough
+// (more than 32 input channels) to repay the taller tile.  Float32 stages 16
+// channels at a time (32 would not leave room for two workgroups per CU), the
+// bf16 modes up to 32; ck is the largest of 32 / 16 / 8 that divides both
+// concatenated inputs.  The choice depends on one image's shape only, so a
+// frame's output does not depend on the batch it is computed in.
+template <int MODE, int BM, int CK, int R>
 hipError_t conv_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
-  constexpr int kTW = 16 * NB;
-  dim3 grid((a.W + kTW - 1) / kTW, (a.H + kTH - 1) / kTH, (cout_pad / BM) * a.batch);
-  conv3x3_kernel<MODE, BM, CK, NB><<<grid, 256, 0, s>>>(a);
-  return hipGetLastError();
-}
-
-template <int MODE, int BM, int NB>
-hipError_t conv_dispatch_ck(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
-  if constexpr (NB == 2 || MODE == 1)
-    if (ck == 32) return conv_launch<MODE, BM, 32, NB>(a, cout_pad, s);
-  if (ck == 16) return conv_launch<MODE, BM, 16, NB>(a, cout_pad, s);
-  if constexpr (MODE == 0)
-    if (ck == 8) return conv_launch<0, BM, 8, NB>(a, cout_pad, s);
-  return hipErrorInvalidValue;
-}
-
-// Tile choice.  Layers with 64+ output channels use 64-channel workgroups with
-// waves of 2 x 32 pixels, unless that grid would leave the chip under-filled
-// (fewer than kSmallGridWgs workgroups per image): then 32-channel workgroups double the
-// grid.  32-channel layers in float32 and split bf16 use waves of 2 x 64 pixels
-// (more reuse of each weight fragment) with at most 16 staged channels so the
-// wider LDS tile stays within 64 KB; plain bf16 measured faster with 2 x 32.
-#ifndef LNR_CONV_SMALL_GRID_WGS
-#define LNR_CONV_SMALL_GRID_WGS 768
-#endif
-#ifndef LNR_CONV_F32_MAX_CK
-#define LNR_CONV_F32_MAX_CK 32
-#endif
-constexpr long kSmallGridWgs = LNR_CONV_SMALL_GRID_WGS;
-#ifndef LNR_CONV_BF16_ROW_REUSE
-#define LNR_CONV_BF16_ROW_REUSE 1
-#endif
-constexpr bool kBf16RowReuse = LNR_CONV_BF16_ROW_REUSE != 0;
-
-template <int BM, int CK>
-hipError_t conv_rows_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
-  constexpr int R = 4;
   dim3 grid((a.W + 31) / 32, (a.H + 4 * R - 1) / (4 * R), (cout_pad / BM) * a.batch);
-  conv3x3_rows_bf16_kernel<BM, CK, R><<<grid, 256, 0, s>>>(a);
+  conv3x3_kernel<MODE, BM, CK, R><<<grid, 256, 0, s>>>(a);
   return hipGetLastError();
-}
-
-template <int BM>
-hipError_t conv_rows_dispatch_ck(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
-  if (ck == 32) return conv_rows_launch<BM, 32>(a, cout_pad, s);
-  if (ck == 16) return conv_rows_launch<BM, 16>(a, cout_pad, s);
-  return hipErrorInvalidValue;
 }
 
 template <int MODE>
 hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
-  if constexpr (MODE == 1) {
-    // row reuse measured faster at 128 output channels and 270x480 pixels
-    // (510 workgroups), slower at 256 channels on 135x240 (288 workgroups)
-    // and mixed at 32 and 64 channels: keep it to wide layers with enough
-    // 32x16 tiles to occupy the chip.  Like the small-grid switch below, the
-    // choice looks at one image only, so a frame's output does not depend on
-    // the batch it was served in.
-    const long rows_wgs = (long)((a.W + 31) / 32) * ((a.H + 15) / 16) * (cout_pad / 64);
-    if (kBf16RowReuse && cout_pad >= 128 && cout_pad % 64 == 0 && rows_wgs >= 384)
-      return conv_rows_dispatch_ck<64>(a, ck, cout_pad, s);
-  }
-  const long tiles = (long)((a.W + 31) / 32) * ((a.H + kTH - 1) / kTH);
-  const bool small = kSmallGridWgs > 0 && tiles * (cout_pad / 64) < kSmallGridWgs;
-  if (cout_pad % 64 == 0 && !small) {
-    const int ck64 = (MODE == 0 && ck > LNR_CONV_F32_MAX_CK) ? LNR_CONV_F32_MAX_CK : ck;
-    return conv_dispatch_ck<MODE, 64, 2>(a, ck64, cout_pad, s);
-  }
-  if constexpr (MODE == 1) {
-    return conv_dispatch_ck<MODE, 32, 2>(a, ck, cout_pad, s);
+  const bool wide = cout_pad % 64 == 0;
+  if constexpr (MODE == 0) {
+    if (ck == 8) return wide ? conv_launch<0, 64, 8, 2>(a, cout_pad, s) : conv_launch<0, 32, 8, 4>(a, cout_pad, s);
+    return wide ? conv_launch<0, 64, 16, 2>(a, cout_pad, s) : conv_launch<0, 32, 16, 4>(a, cout_pad, s);
+  } else if constexpr (MODE == 1) {
+    if (ck < 16) return hipErrorInvalidValue;
+    if (wide) return ck == 32 ? conv_launch<1, 64, 32, 2>(a, cout_pad, s) : conv_launch<1, 64, 16, 2>(a, cout_pad, s);
+    if (a.C0 + a.C1 > 32)
+      return ck == 32 ? conv_launch<1, 32, 32, 4>(a, cout_pad, s) : conv_launch<1, 32, 16, 4>(a, cout_pad, s);
+    return ck == 32 ? conv_launch<1, 32, 32, 2>(a, cout_pad, s) : conv_launch<1, 32, 16, 2>(a, cout_pad, s);
   } else {
-    if (cout_pad > 32) return conv_dispatch_ck<MODE, 32, 2>(a, ck, cout_pad, s);
-    return conv_dispatch_ck<MODE, 32, 4>(a, ck < 16 ? ck : 16, cout_pad, s);
+    if (ck < 16) return hipErrorInvalidValue;
+    return wide ? conv_launch<2, 64, 16, 2>(a, cout_pad, s) : conv_launch<2, 32, 16, 4>(a, cout_pad, s);
   }
 }
 

@@ -163,3 +163,23 @@ def test_soft_zbuffer_rejects_bad_eps(lnr, ctx, room_cloud, room_cams):
         with pytest.raises(lnr.LnrError) as e:
             lnr.lnr_render_soft(ctx, room_cloud, cam, lnr.Image(cam.height, cam.width), eps)
         assert e.value.status == lnr.LNR_E_INVALID_ARG
+
+
+def test_objects_outlive_a_destroyed_context(lnr, ctx, room_scene, room_grid, room_cams):
+    """Destroying a context before its cloud and network (as a garbage
+    collector may) keeps them usable and leaves no error behind for later
+    calls: the context is freed with its last object."""
+    import torch
+    c1 = lnr.lnr_context_create(0)
+    cloud = lnr.lnr_cloud_load(c1, room_scene.xyz, room_scene.rgb, 0.5)
+    net = lnr.lnr_unet_load(c1, synth.make_unet_blob((16, 32), seed=0), lnr.LNR_BF16)
+    lnr.lnr_context_destroy(c1)
+    cam = room_cams[3]
+    assert_images_equal(image_to_host(render_gpu(lnr, ctx, cloud, cam)), R.render(room_grid, cam), "after destroy")
+    out = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device="cuda")
+    lnr.lnr_reconstruct(ctx, net, render_gpu(lnr, ctx, cloud, cam), out)
+    torch.cuda.synchronize()
+    lnr.lnr_unet_destroy(net)
+    lnr.lnr_cloud_destroy(cloud)    # frees the context too
+    fresh = lnr.lnr_cloud_load(ctx, room_scene.xyz, room_scene.rgb, 0.5)
+    assert_images_equal(image_to_host(render_gpu(lnr, ctx, fresh, cam)), R.render(room_grid, cam), "fresh cloud")
