@@ -216,51 +216,83 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   constexpr int G = T::kGroup, HG = G / 2;
   const LT *bbase = s_in + (wv * R * LW + n) * S + HG * h;
   const LT *abase = s_w + n * 9 * S + HG * h;
-  auto compute = [&]() {
-#pragma unroll 1
-    for (int g = 0; g < CK / G; ++g) {
-      const LT *ag = abase + g * G, *bg = bbase + g * G;
+  // one step = one horizontal tap offset dx of one channel group: the
+  // fragments of step s + 1 are read from LDS while the MFMAs of step s run
+  constexpr int NSTEP = (CK / G) * 3;
+  struct Frags {
+    uint4 a[T::kPlanes][MB][3], b[T::kPlanes][R + 2];
+  };
+  auto load_frags = [&](int st, Frags &f) {
+    const int g = st / 3, dx = st - 3 * g;
+    const LT *ag = abase + g * G, *bg = bbase + g * G;
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        uint4 av[T::kPlanes][MB][3], bv[T::kPlanes][R + 2];
+    for (int p = 0; p < T::kPlanes; ++p) {
 #pragma unroll
-        for (int p = 0; p < T::kPlanes; ++p) {
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-              av[p][mb][dy] = *reinterpret_cast<const uint4 *>(ag + p * WP + (mb * 32 * 9 + dy * 3 + dx) * S);
-#pragma unroll
-          for (int i = 0; i < R + 2; ++i)
-            bv[p][i] = *reinterpret_cast<const uint4 *>(bg + p * INP + (i * LW + dx) * S);
-        }
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy)
+          f.a[p][mb][dy] = *reinterpret_cast<const uint4 *>(ag + p * WP + (mb * 32 * 9 + dy * 3 + dx) * S);
 #pragma unroll
-          for (int r = 0; r < R; ++r)
+      for (int i = 0; i < R + 2; ++i) f.b[p][i] = *reinterpret_cast<const uint4 *>(bg + p * INP + (i * LW + dx) * S);
+    }
+  };
+  auto mma = [&](const Frags &f) {
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-              if constexpr (MODE == 0) {
-                const float4 av4 = __builtin_bit_cast(float4, av[0][mb][dy]);
-                const float4 bv4 = __builtin_bit_cast(float4, bv[0][r + dy]);
-                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.x, bv4.x, acc[mb][r], 0, 0, 0);
-                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.y, bv4.y, acc[mb][r], 0, 0, 0);
-                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.z, bv4.z, acc[mb][r], 0, 0, 0);
-                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.w, bv4.w, acc[mb][r], 0, 0, 0);
-              } else if constexpr (MODE == 1) {
-                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av[0][mb][dy]), as_bf16x8(bv[0][r + dy]),
-                                                                     acc[mb][r], 0, 0, 0);
-              } else {
-                const int P1 = T::kPlanes - 1;  // lo plane
-                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av[P1][mb][dy]), as_bf16x8(bv[0][r + dy]),
-                                                                     acc[mb][r], 0, 0, 0);
-                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av[0][mb][dy]), as_bf16x8(bv[P1][r + dy]),
-                                                                     acc[mb][r], 0, 0, 0);
-                acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av[0][mb][dy]), as_bf16x8(bv[0][r + dy]),
-                                                                     acc[mb][r], 0, 0, 0);
-              }
-            }
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          if constexpr (MODE == 0) {
+            const float4 av4 = __builtin_bit_cast(float4, f.a[0][mb][dy]);
+            const float4 bv4 = __builtin_bit_cast(float4, f.b[0][r + dy]);
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.x, bv4.x, acc[mb][r], 0, 0, 0);
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.y, bv4.y, acc[mb][r], 0, 0, 0);
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.z, bv4.z, acc[mb][r], 0, 0, 0);
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.w, bv4.w, acc[mb][r], 0, 0, 0);
+          } else if constexpr (MODE == 1) {
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(f.a[0][mb][dy]), as_bf16x8(f.b[0][r + dy]),
+                                                                 acc[mb][r], 0, 0, 0);
+          } else {
+            const int P1 = T::kPlanes - 1;  // lo plane
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(f.a[P1][mb][dy]), as_bf16x8(f.b[0][r + dy]),
+                                                                 acc[mb][r], 0, 0, 0);
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(f.a[0][mb][dy]), as_bf16x8(f.b[P1][r + dy]),
+                                                                 acc[mb][r], 0, 0, 0);
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(f.a[0][mb][dy]), as_bf16x8(f.b[0][r + dy]),
+                                                                 acc[mb][r], 0, 0, 0);
+          }
+        }
+  };
+  auto compute = [&]() {
+    if constexpr (MODE == 0) {
+      // float32 MFMAs are long (64 cycles each, 4 per fragment pair): no need
+      // to hold two steps of fragments
+#pragma unroll 1
+      for (int g = 0; g < CK / G; ++g) {
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          Frags f;
+          load_frags(3 * g + dx, f);
+          mma(f);
+        }
       }
+    } else {
+      Frags f0, f1;
+      load_frags(0, f0);
+#pragma unroll
+      for (int st = 0; st < NSTEP; st += 2) {
+        if (st + 1 < NSTEP) load_frags(st + 1, f1);
+        mma(f0);
+        if (st + 1 < NSTEP) {
+          if (st + 2 < NSTEP) load_frags(st + 2, f0);
+          mma(f1);
+        }
+      }
+      // scheduler strategy for MFMA / LDS-read interleaving (measured: 1 for
+      // bf16, 0 for the three-pass split mode)
+      if constexpr (MODE == 1) __builtin_amdgcn_iglp_opt(1);
+      else __builtin_amdgcn_iglp_opt(0);
     }
   };
   {
@@ -376,9 +408,10 @@ __global__ __launch_bounds__(256) void pack_kernel(const float *__restrict__ dep
   v[2] = (float)((q >> 16) & 255u) / 255.0f;
   v[3] = A ? depth[p] * 0.0625f : 0.f;
   v[4] = A ? 1.f : 0.f;
-  if (MODE == 1) {
-    uint16_t *o = static_cast<uint16_t *>(x) + (size_t)p * cpad;
-    for (int i = 0; i < cpad; i += 2) *reinterpret_cast<uint32_t *>(o + i) = pack_bf16x2(v[i], v[i + 1]);
+  if (MODE == 1) {  // cpad is 16: two 16-byte stores
+    uint4 *o = reinterpret_cast<uint4 *>(static_cast<uint16_t *>(x) + (size_t)p * cpad);
+    o[0] = make_uint4(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]), pack_bf16x2(v[4], v[5]), pack_bf16x2(v[6], v[7]));
+    o[1] = make_uint4(0u, 0u, 0u, 0u);
   } else {
     float *o = static_cast<float *>(x) + (size_t)p * cpad;
     for (int i = 0; i < cpad; i += 4) *reinterpret_cast<float4 *>(o + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
@@ -419,13 +452,17 @@ __global__ __launch_bounds__(256) void head_kernel(const void *__restrict__ x, i
 
 // Tile choice per layer (measured on the 1080p workload).  64-channel
 // workgroups with 2 rows per wave where the layer has a multiple of 64 output
-// channels; 32-channel layers (the first level) use 4 rows per wave in float32
-// and split bf16, and in bf16 4 rows only when the layer is deep enough
-// (more than 32 input channels) to repay the taller tile.  Float32 stages 16
-// channels at a time (32 would not leave room for two workgroups per CU), the
-// bf16 modes up to 32; ck is the largest of 32 / 16 / 8 that divides both
-// concatenated inputs.  The choice depends on one image's shape only, so a
-// frame's output does not depend on the batch it is computed in.
+// channels; in float32, when one image gives fewer than kSmallGrid such
+// workgroups (the 135x240 level of a 1080p frame), 32-channel workgroups
+// double the grid so the last round of workgroups is not nearly empty (the
+// bf16 modes measured no gain from it).  32-channel layers (the first level)
+// use 2 rows per wave, except deep (more than 32 input channels) bf16 layers,
+// where 4 rows measured faster.  Float32 stages 16 channels at a time (32
+// would not leave room for two workgroups per CU), the bf16 modes up to 32;
+// ck is the largest of 32 / 16 / 8 that divides both concatenated inputs.
+// The choice depends on one image's shape only, so a frame's output does not
+// depend on the batch it is computed in.
+constexpr long kSmallGrid = 768;
 template <int MODE, int BM, int CK, int R>
 hipError_t conv_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
   dim3 grid((a.W + 31) / 32, (a.H + 4 * R - 1) / (4 * R), (cout_pad / BM) * a.batch);
@@ -436,18 +473,21 @@ hipError_t conv_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
 template <int MODE>
 hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
   const bool wide = cout_pad % 64 == 0;
+  const bool small = (long)((a.W + 31) / 32) * ((a.H + 7) / 8) * (cout_pad / 64) < kSmallGrid;
   if constexpr (MODE == 0) {
-    if (ck == 8) return wide ? conv_launch<0, 64, 8, 2>(a, cout_pad, s) : conv_launch<0, 32, 8, 4>(a, cout_pad, s);
-    return wide ? conv_launch<0, 64, 16, 2>(a, cout_pad, s) : conv_launch<0, 32, 16, 4>(a, cout_pad, s);
+    if (ck == 8) return wide ? conv_launch<0, 64, 8, 2>(a, cout_pad, s) : conv_launch<0, 32, 8, 2>(a, cout_pad, s);
+    return (wide && !small) ? conv_launch<0, 64, 16, 2>(a, cout_pad, s) : conv_launch<0, 32, 16, 2>(a, cout_pad, s);
   } else if constexpr (MODE == 1) {
     if (ck < 16) return hipErrorInvalidValue;
-    if (wide) return ck == 32 ? conv_launch<1, 64, 32, 2>(a, cout_pad, s) : conv_launch<1, 64, 16, 2>(a, cout_pad, s);
+    if (wide)
+      return ck == 32 ? conv_launch<1, 64, 32, 2>(a, cout_pad, s) : conv_launch<1, 64, 16, 2>(a, cout_pad, s);
     if (a.C0 + a.C1 > 32)
       return ck == 32 ? conv_launch<1, 32, 32, 4>(a, cout_pad, s) : conv_launch<1, 32, 16, 4>(a, cout_pad, s);
     return ck == 32 ? conv_launch<1, 32, 32, 2>(a, cout_pad, s) : conv_launch<1, 32, 16, 2>(a, cout_pad, s);
   } else {
     if (ck < 16) return hipErrorInvalidValue;
-    return wide ? conv_launch<2, 64, 16, 2>(a, cout_pad, s) : conv_launch<2, 32, 16, 4>(a, cout_pad, s);
+    if (wide) return conv_launch<2, 64, 16, 2>(a, cout_pad, s);
+    return conv_launch<2, 32, 16, 2>(a, cout_pad, s);
   }
 }
 

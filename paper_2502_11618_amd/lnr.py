@@ -166,7 +166,7 @@ class Cloud:
         return lnr_cloud_info(self)
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.lnr_cloud_destroy(self.handle)
             self.handle = None
 
@@ -179,7 +179,7 @@ class UNet:
         self.widths = widths
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.lnr_unet_destroy(self.handle)
             self.handle = None
 
@@ -189,7 +189,7 @@ class Context:
         self.handle = handle
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.lnr_context_destroy(self.handle)
             self.handle = None
 
@@ -369,7 +369,7 @@ class Server:
         self._keep = keep  # the cloud and network must outlive the server
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.lnr_server_destroy(self.handle)
             self.handle = None
 
