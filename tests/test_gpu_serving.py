@@ -110,3 +110,28 @@ def test_superseded_requests_and_admission(lnr, room_scene, room_cloud):
     with pytest.raises(lnr.LnrError) as e:
         lnr.lnr_server_open_session(srv_s, 64, 64)
     assert e.value.status == lnr.LNR_E_BUDGET
+
+
+def test_soft_zbuffer_sessions_equal_alone(lnr, ctx, room_scene, room_cloud):
+    """Serving with the soft z-buffer: every frame equals lnr_render_soft +
+    filter + reconstruct of the same camera."""
+    import torch
+    blob = synth.make_unet_blob((16, 32, 64), seed=1)
+    net = lnr.lnr_unet_load(ctx, blob, lnr.LNR_FP32)
+    srv = lnr.lnr_server_create(ctx, room_cloud, net, max_batch=4, lanes=2, n_levels=3, filter_strength=0.5,
+                                soft=True, soft_eps=0.02, use_graphs=True, max_width=128, max_height=96)
+    sizes = [(128, 96), (64, 64), (128, 96)]
+    sids = [lnr.lnr_server_open_session(srv, w, h) for (w, h) in sizes]
+    cams = [synth.random_walk_path(room_scene, 2, seed=30 + i, width=w, height=h, fov_deg=80.0)
+            for i, (w, h) in enumerate(sizes)]
+    res = _serve_all(lnr, srv, sids, cams, 2)
+    for f in range(2):
+        for i, (w, h) in enumerate(sizes):
+            cam = cams[i][f]
+            img = lnr.Image(h, w)
+            lnr.lnr_render_soft(ctx, room_cloud, cam, img, 0.02)
+            lnr.lnr_depth_filter(ctx, img, 3, 0.5)
+            out = torch.empty((3, h, w), dtype=torch.float32, device="cuda")
+            lnr.lnr_reconstruct(ctx, net, img, out)
+            torch.cuda.synchronize()
+            assert np.array_equal(res[f * 100 + i][0], out.cpu().numpy()), f"session {i} frame {f}"
