@@ -161,9 +161,10 @@ def _sources_sha():
 def summarize_counters(args):
     """Per-kernel HBM bytes from rocprofv3 --pmc csv files of a float32 frames
     run, each counter scaled by what it reads for a plain 1 GiB device copy.
-    Convolutions are named by their place in the frame (the n-th conv3x3
-    dispatch after each pack dispatch is the n-th layer of conv_shapes), so the
-    figures stay tied to layers whatever template a layer dispatches to.
+    Convolutions are named by their place in the frame (a frame's first
+    convolution is the one that stages the RGBDA image, or follows the input
+    pack; the n-th after it is the n-th layer of conv_shapes), so the figures
+    stay tied to layers whatever template a layer dispatches to.
     Writes every layer's figures next to the hash of the sources that decide
     them."""
     import collections
@@ -194,7 +195,9 @@ def summarize_counters(args):
             name = short(r["Kernel_Name"])
             if name.startswith("pack_kernel"):
                 conv_i = 0
-            elif name.startswith("conv3x3") and conv_i is not None and conv_i < len(layer_names):
+            if name.startswith("conv3x3") and name.endswith(", true>"):
+                conv_i = 0  # the first convolution stages the RGBDA image itself
+            if name.startswith("conv3x3") and conv_i is not None and conv_i < len(layer_names):
                 kname[layer_names[conv_i]] = name
                 name = layer_names[conv_i]
                 conv_i += 1

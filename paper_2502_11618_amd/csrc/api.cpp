@@ -321,7 +321,8 @@ lnr_status unet_pack(lnr_context *ctx, Scratch &sc, const lnr_unet *u, const UNe
 // into the last one when widths[0] <= 64 (outputs: head_outs_dev[b] if given,
 // else rgb_out + b * 3*H*W), otherwise it runs as its own kernel per image.
 lnr_status unet_convs(lnr_context *ctx, Scratch &sc, const lnr_unet *u, const UNetLayout &y, float *rgb_out,
-                      float *const *head_outs_dev, hipStream_t s) {
+                      float *const *head_outs_dev, hipStream_t s, const float *rgbda_depth = nullptr,
+                      const uint32_t *rgbda_rgba = nullptr) {
   char *base = static_cast<char *>(sc.act.p);
   const int L = u->L, B = y.B;
   const bool fuse_head = u->widths[0] <= 64;
@@ -341,6 +342,10 @@ lnr_status unet_convs(lnr_context *ctx, Scratch &sc, const lnr_unet *u, const UN
     a.out = base + y.t_off[l];
     a.out_bs = y.act_bs[l];
     a.batch = B;
+    if (l == 0 && rgbda_depth) {
+      a.rgbda_depth = rgbda_depth;
+      a.rgbda_rgba = rgbda_rgba;
+    }
     LNR_LAUNCH(ctx, kConvNames[0][l][0], s, launch_conv3x3(a, u->prec, s));
     ConvCall c{};
     c.in0 = base + y.t_off[l];
@@ -947,9 +952,11 @@ lnr_status lnr_reconstruct(lnr_context *ctx, const lnr_unet *u, const lnr_image 
   const UNetLayout lay = unet_layout(u, H, W, 1);
   if ((st = ensure(ctx, ctx->sc.act, lay.bytes)) != LNR_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if ((st = unet_pack(ctx, ctx->sc, u, lay, 0, in->depth, reinterpret_cast<const uint32_t *>(in->rgba), s)) != LNR_OK)
+  // one image: the first convolution reads the RGBDA image itself (batches
+  // from the serving loop go through the input pack into one batched tensor)
+  if ((st = unet_convs(ctx, ctx->sc, u, lay, rgb_out, nullptr, s, in->depth,
+                       reinterpret_cast<const uint32_t *>(in->rgba))) != LNR_OK)
     return st;
-  if ((st = unet_convs(ctx, ctx->sc, u, lay, rgb_out, nullptr, s)) != LNR_OK) return st;
   ctx->last_stream = s;
   return LNR_OK;
 }

@@ -122,6 +122,10 @@ struct ConvCall {
   int batch = 1;
   size_t in0_bs = 0, in1_bs = 0, out_bs = 0, pool_bs = 0;
   float *const *head_outs = nullptr;
+  // first layer of a single image only: stage the network input straight from
+  // the RGBDA image (the same values the input pack writes) instead of in0
+  const float *rgbda_depth = nullptr;
+  const uint32_t *rgbda_rgba = nullptr;
 };
 
 hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, int W, int cpad, Prec p, void *x,

@@ -46,6 +46,8 @@ struct ConvArgs {
   int batch;
   size_t in0_bs, in1_bs, out_bs, pool_bs;
   float *const *head_outs;
+  const float *rgbda_depth;
+  const uint32_t *rgbda_rgba;
 };
 
 // 3x3 convolution as implicit GEMM (M = output channels, N = pixels, K = 9 taps
@@ -102,7 +104,7 @@ struct ConvTraits<2> {  // float32 activations, split bf16 operands
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
-template <int MODE, int BM, int CK, int R>
+template <int MODE, int BM, int CK, int R, bool RGBDA>
 __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   using T = ConvTraits<MODE>;
   using LT = typename T::L;
@@ -165,8 +167,28 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 #pragma unroll
     for (int k = 0; k < NIN; ++k) {
       const int o = from0 ? off0[k] : off1[k];
-      const uint4 v = *reinterpret_cast<const uint4 *>(src + (size_t)(o < 0 ? 0 : o) * csrc);
-      pin[k] = o < 0 ? make_uint4(0u, 0u, 0u, 0u) : v;
+      if constexpr (RGBDA) {
+        // network input x = (r/255, g/255, b/255, A ? D/16 : 0, A, 0, ...),
+        // computed as the input pack computes it; this thread's vector holds
+        // channels [qi, qi + kInVec)
+        const size_t oc = (size_t)(o < 0 ? 0 : o);
+        const uint32_t q = a.rgbda_rgba[oc];
+        const float d = a.rgbda_depth[oc];
+        const bool A = (q >> 24) != 0;
+        const float x0 = (float)(q & 255u) / 255.0f, x1 = (float)((q >> 8) & 255u) / 255.0f;
+        const float x2 = (float)((q >> 16) & 255u) / 255.0f, x3 = A ? d * 0.0625f : 0.f, x4 = A ? 1.f : 0.f;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (MODE == 1) {
+          if (qi == 0) v = make_uint4(pack_bf16x2(x0, x1), pack_bf16x2(x2, x3), pack_bf16x2(x4, 0.f), 0u);
+        } else {
+          if (qi == 0) v = make_uint4(__float_as_uint(x0), __float_as_uint(x1), __float_as_uint(x2), __float_as_uint(x3));
+          if (qi == 4) v = make_uint4(__float_as_uint(x4), 0u, 0u, 0u);
+        }
+        pin[k] = o < 0 ? make_uint4(0u, 0u, 0u, 0u) : v;
+      } else {
+        const uint4 v = *reinterpret_cast<const uint4 *>(src + (size_t)(o < 0 ? 0 : o) * csrc);
+        pin[k] = o < 0 ? make_uint4(0u, 0u, 0u, 0u) : v;
+      }
     }
 #pragma unroll
     for (int k = 0; k < NWR; ++k) {
@@ -466,7 +488,15 @@ constexpr long kSmallGrid = 768;
 template <int MODE, int BM, int CK, int R>
 hipError_t conv_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
   dim3 grid((a.W + 31) / 32, (a.H + 4 * R - 1) / (4 * R), (cout_pad / BM) * a.batch);
-  conv3x3_kernel<MODE, BM, CK, R><<<grid, 256, 0, s>>>(a);
+  if (a.rgbda_depth) {
+    // only the network's first layer (one staged chunk of cin0_pad channels)
+    if constexpr (CK == ConvTraits<MODE>::kGroup)
+      conv3x3_kernel<MODE, BM, CK, R, true><<<grid, 256, 0, s>>>(a);
+    else
+      return hipErrorInvalidValue;
+  } else {
+    conv3x3_kernel<MODE, BM, CK, R, false><<<grid, 256, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -508,8 +538,9 @@ hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s) {
   const ConvLayer &L = *c.layer;
   ConvArgs a{c.in0, c.in1, c.C0, c.C1, c.H, c.W, L.w, L.w_lo, L.bias, L.cout, L.cin_pad, c.out, c.out_pool,
              c.head_w, c.head_b, c.head_out, c.batch < 1 ? 1 : c.batch, c.in0_bs, c.in1_bs, c.out_bs, c.pool_bs,
-             c.head_outs};
+             c.head_outs, c.rgbda_depth, c.rgbda_rgba};
   if (c.head_out && (L.cout_pad > 64 || c.out_pool)) return hipErrorInvalidValue;
+  if (c.rgbda_depth && (!c.rgbda_rgba || c.C1 != 0 || c.batch > 1)) return hipErrorInvalidValue;
   const int step = (p == Prec::F32) ? 8 : 16;
   int ck = 32;
   while (ck > step && ((c.C0 % ck) != 0 || (c.C1 % ck) != 0)) ck >>= 1;
