@@ -318,6 +318,76 @@ def serve_bench(L, scene, cloud, blob, seconds, n_sessions=64, seed=0, budget=32
     }
 
 
+def precision_tier(args):
+    """The precision tier on the larger scene: 100M points from 8 scans (1 m
+    cells), 60 frames of the orbit path at 1920x1080 and at 2560x1440, depth
+    filter n = 5, fs = 0.5, U-Net 32/64/128/256 in fp32, split bf16 and bf16:
+    frames/s, per-frame latency and the sampled error against the float64
+    oracle of each precision.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2502_11618_amd as L
+    import synth
+
+    FOV, NL, FS, STEPS = 90.0, 5, 0.5, 60
+    widths = (32, 64, 128, 256)
+    t0 = time.perf_counter()
+    scene = synth.scene_for_config("large", seed=0)
+    log(f"scene {scene.name}: {scene.n} points ({time.perf_counter() - t0:.1f} s)")
+    blob = synth.make_unet_blob(widths, seed=0)
+    ctx = L.lnr_context_create(0)
+    t0 = time.perf_counter()
+    cloud = L.lnr_cloud_load(ctx, scene.xyz, scene.rgb, 1.0)
+    load_s = time.perf_counter() - t0
+    prec_ids = {"fp32": L.LNR_FP32, "bf16x3": L.LNR_BF16X3, "bf16": L.LNR_BF16}
+    nets = {p: L.lnr_unet_load(ctx, blob, i) for p, i in prec_ids.items()}
+    out_all = {}
+    for W, H in ((1920, 1080), (2560, 1440)):
+        cams = synth.orbit_path(scene, 120, W, H, FOV)
+        img = L.Image(H, W)
+        out = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
+        res = {}
+        for p, net in nets.items():
+            for i in range(5):
+                L.lnr_render(ctx, cloud, cams[i], img)
+                L.lnr_depth_filter(ctx, img, NL, FS)
+                L.lnr_reconstruct(ctx, net, img, out)
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(STEPS)]
+            t0 = time.perf_counter()
+            for i in range(STEPS):
+                ev[i][0].record()
+                L.lnr_render(ctx, cloud, cams[2 * i], img)
+                L.lnr_depth_filter(ctx, img, NL, FS)
+                L.lnr_reconstruct(ctx, net, img, out)
+                ev[i][1].record()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            lat = np.array([a.elapsed_time(b) for a, b in ev])
+            res[p] = {"frames_per_s": round(STEPS / wall, 2), "ms_per_frame": round(1000 * wall / STEPS, 4),
+                      "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                                     "p99": round(float(np.percentile(lat, 99)), 4)}}
+        L.lnr_render(ctx, cloud, cams[0], img)
+        L.lnr_depth_filter(ctx, img, NL, FS)
+        torch.cuda.synchronize()
+        _, proc, _ = L.lnr_render_stats(ctx)
+        fd, fr = img.depth.cpu().numpy(), img.rgba.cpu().numpy()
+        outs = {}
+        for p, net in nets.items():
+            L.lnr_reconstruct(ctx, net, img, out)
+            torch.cuda.synchronize()
+            outs[p] = out.cpu().numpy().astype(np.float64)
+        err = sampled_error(fd, fr, blob, outs, H, W)
+        for p in res:
+            res[p]["error_vs_fp64_sampled"] = err[p]
+        out_all[f"{W}x{H}"] = {"processed_points_frame0": proc, "precisions": res}
+        log(f"{W}x{H}: " + ", ".join(f"{p} {r['frames_per_s']} f/s" for p, r in res.items()))
+    print(json.dumps({"mode": "precision-tier", "workload": "large-100M-pts-8-scans-orbit",
+                      "points": scene.n, "cell_m": 1.0, "load_partition_s": round(load_s, 3), "n_levels": NL,
+                      "filter_strength": FS, "unet_widths": list(widths), "steps": STEPS, "results": out_all,
+                      "env": host_info()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,9 +398,10 @@ def main():
     ap.add_argument("--precisions", default="fp32,bf16x3,bf16")
     ap.add_argument("--no-error-check", action="store_true", help="skip the float64 error windows")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="serving run length (0 = skip)")
-    ap.add_argument("--mode", default="frames", choices=["frames", "copy", "counters"],
+    ap.add_argument("--mode", default="frames", choices=["frames", "copy", "counters", "precision-tier"],
                     help="copy: only a plain 1 GiB device copy (calibrates HBM byte counters); "
-                         "counters: summarise rocprofv3 FETCH_SIZE/WRITE_SIZE csv files (no GPU)")
+                         "counters: summarise rocprofv3 FETCH_SIZE/WRITE_SIZE csv files (no GPU); "
+                         "precision-tier: the 100M-point scene at 1080p and 1440p in all three precisions")
     ap.add_argument("--fetch-csv", help="counters mode: FETCH_SIZE counter_collection.csv of a frames run")
     ap.add_argument("--write-csv", help="counters mode: WRITE_SIZE counter_collection.csv of a frames run")
     ap.add_argument("--copy-fetch-csv", help="counters mode: FETCH_SIZE csv of a copy run")
@@ -347,6 +418,9 @@ def main():
     import numpy as np
     import torch
 
+    if args.mode == "precision-tier":
+        precision_tier(args)
+        return
     if args.mode == "copy":
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)

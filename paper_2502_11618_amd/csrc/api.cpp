@@ -252,6 +252,8 @@ CullParams make_cull_params(const lnr_camera *cam, bool no_cull) {
   for (int r = 0; r < 3; ++r)
     for (int k = 0; k < 4; ++k) p.absP[r][k] = std::fabs(P[r][k]);
   p.wh1 = (Wd + Hd) + 1.0;
+  for (int k = 0; k < 4; ++k) p.wrow[k] = w[k];
+  p.z_near = n64;
   p.no_cull = no_cull ? 1 : 0;
   return p;
 }
@@ -653,8 +655,9 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   if (st != LNR_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if ((st = ensure(ctx, scr.flags, c->d.n_cells)) != LNR_OK) return st;
-  if ((st = ensure(ctx, scr.chunks, 8ull * std::max<uint32_t>(1, c->d.max_chunks))) != LNR_OK) return st;
-  if ((st = ensure(ctx, scr.counters, 256)) != LNR_OK) return st;
+  if ((st = ensure(ctx, scr.chunks, 8ull * kDepthBuckets * std::max<uint32_t>(1, c->d.max_chunks))) != LNR_OK)
+    return st;
+  if ((st = ensure(ctx, scr.counters, 4 * kCounterWords)) != LNR_OK) return st;
   const uint32_t npix = (uint32_t)cam->width * (uint32_t)cam->height;
   uint32_t *counters = static_cast<uint32_t *>(scr.counters.p);
   const CullParams prm = make_cull_params(cam, (flags & LNR_RENDER_NO_CULL) != 0);
@@ -1145,8 +1148,8 @@ lnr_status lnr_server_create(lnr_context *ctx, const lnr_cloud *c, const lnr_une
       return hip_fail(ctx, e, "server lane setup");
     }
     if ((st = ensure(ctx, l.sc.flags, c->d.n_cells)) != LNR_OK ||
-        (st = ensure(ctx, l.sc.chunks, 8ull * std::max<uint32_t>(1, c->d.max_chunks))) != LNR_OK ||
-        (st = ensure(ctx, l.sc.counters, 256)) != LNR_OK || (st = ensure(ctx, l.sc.pyramid, pyr)) != LNR_OK ||
+        (st = ensure(ctx, l.sc.chunks, 8ull * kDepthBuckets * std::max<uint32_t>(1, c->d.max_chunks))) != LNR_OK ||
+        (st = ensure(ctx, l.sc.counters, 4 * kCounterWords)) != LNR_OK || (st = ensure(ctx, l.sc.pyramid, pyr)) != LNR_OK ||
         (st = ensure(ctx, l.sc.act, act)) != LNR_OK ||
         (cfg->soft && (st = ensure(ctx, l.sc.soft_acc, 16 * npix)) != LNR_OK) ||
         (st = dalloc(ctx, (void **)&l.head_outs_dev, 8ull * 16)) != LNR_OK) {

@@ -30,25 +30,28 @@ __global__ __launch_bounds__(kThreads) void clear_kernel(uint64_t *__restrict__ 
 
 // One lane per cell.  A non-empty cell is visible unless some half-space's
 // maximum over the cell's box is below -slack (all in double, in the order
-// below).  Visible cells are compacted into splat work items of at most
-// kSplatChunk points with a wave-wide prefix sum and one atomic per wave.
+// below).  Visible cells are cut into splat work items of at most kSplatChunk
+// points, queued in the depth bucket of the cell's centre; the totals are
+// reduced per wave with one atomic per wave.
 __global__ __launch_bounds__(kThreads) void cull_kernel(const float *__restrict__ aabb,
                                                         const uint32_t *__restrict__ cell_start, uint32_t n_cells,
                                                         CullParams prm, uint8_t *__restrict__ flags,
-                                                        uint2 *__restrict__ chunks, uint32_t *__restrict__ counters) {
+                                                        uint2 *__restrict__ chunks, uint32_t cap,
+                                                        uint32_t *__restrict__ counters) {
   const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
   const int lane = threadIdx.x & 63;
   uint32_t start = 0, cnt = 0;
   bool vis = false;
+  int bucket = 0;
   if (c < n_cells) {
     start = cell_start[c];
     cnt = cell_start[c + 1] - start;
     if (cnt > 0) {
+      const double lo0 = aabb[6ull * c + 0], lo1 = aabb[6ull * c + 1], lo2 = aabb[6ull * c + 2];
+      const double hi0 = aabb[6ull * c + 3], hi1 = aabb[6ull * c + 4], hi2 = aabb[6ull * c + 5];
       if (prm.no_cull) {
         vis = true;
       } else {
-        const double lo0 = aabb[6ull * c + 0], lo1 = aabb[6ull * c + 1], lo2 = aabb[6ull * c + 2];
-        const double hi0 = aabb[6ull * c + 3], hi1 = aabb[6ull * c + 4], hi2 = aabb[6ull * c + 5];
         const double mx0 = fmax(fabs(lo0), fabs(hi0));
         const double mx1 = fmax(fabs(lo1), fabs(hi1));
         const double mx2 = fmax(fabs(lo2), fabs(hi2));
@@ -64,32 +67,60 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(const float *__restrict_
           if (m < -slack) vis = false;
         }
       }
+      if (vis) {
+        // camera depth of the box centre -> bucket
+        const double cw = ((prm.wrow[0] * (0.5 * (lo0 + hi0)) + prm.wrow[1] * (0.5 * (lo1 + hi1))) +
+                           prm.wrow[2] * (0.5 * (lo2 + hi2))) + prm.wrow[3];
+        const float q = cw > prm.z_near ? kBucketsPerOctave * __log2f((float)(cw / prm.z_near)) : 0.f;
+        bucket = q >= (float)(kDepthBuckets - 1) ? kDepthBuckets - 1 : (int)q;
+      }
     }
     flags[c] = vis ? 1 : 0;
   }
-  // wave-wide compaction of the visible cells' work items
+  // this cell's work items go to its bucket's queue: places are reserved per
+  // block in LDS, then with one global atomic per bucket
+  __shared__ uint32_t s_n[kDepthBuckets], s_base[kDepthBuckets];
+  if (threadIdx.x < kDepthBuckets) s_n[threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t nch = vis ? (cnt + kSplatChunk - 1) / kSplatChunk : 0u;
-  uint32_t incl = nch;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t t = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += t;
+  const uint32_t local = nch ? atomicAdd(&s_n[bucket], nch) : 0u;
+  __syncthreads();
+  if (threadIdx.x < kDepthBuckets && s_n[threadIdx.x])
+    s_base[threadIdx.x] = atomicAdd(&counters[4 + threadIdx.x], s_n[threadIdx.x]);
+  __syncthreads();
+  if (nch) {
+    const uint32_t pos = s_base[bucket] + local;
+    for (uint32_t k = 0; k < nch; ++k) {
+      const uint32_t off = k * kSplatChunk;
+      chunks[(size_t)bucket * cap + pos + k] = make_uint2(start + off, min(kSplatChunk, cnt - off));
+    }
   }
-  const uint32_t wave_chunks = __shfl(incl, 63, 64);
+  uint32_t wave_chunks = nch;
+  for (int off = 32; off > 0; off >>= 1) wave_chunks += __shfl_xor(wave_chunks, off, 64);
   const uint64_t vis_mask = __ballot(vis);
   uint32_t pts = vis ? cnt : 0u;
   for (int off = 32; off > 0; off >>= 1) pts += __shfl_xor(pts, off, 64);
-  uint32_t base = 0;
   if (lane == 0 && wave_chunks) {
-    base = atomicAdd(&counters[0], wave_chunks);
+    atomicAdd(&counters[0], wave_chunks);
     atomicAdd(&counters[1], (uint32_t)__popcll(vis_mask));
     atomicAdd(reinterpret_cast<unsigned long long *>(&counters[2]), (unsigned long long)pts);
   }
-  base = __shfl(base, 0, 64);
-  uint32_t pos = base + incl - nch;
-  for (uint32_t k = 0; k < nch; ++k) {
-    const uint32_t off = k * kSplatChunk;
-    chunks[pos + k] = make_uint2(start + off, min(kSplatChunk, cnt - off));
+}
+
+// Work item `i` of the frame, walking the depth-bucket queues nearest first
+// (counters[4 + b] items in bucket b); false past the last item.
+__device__ inline bool work_item(uint32_t i, const uint32_t *__restrict__ counters, const uint2 *__restrict__ chunks,
+                                 uint32_t cap, uint2 *ch) {
+  if (i >= counters[0]) return false;
+  for (int b = 0; b < kDepthBuckets; ++b) {
+    const uint32_t nb = counters[4 + b];
+    if (i < nb) {
+      *ch = chunks[(size_t)b * cap + i];
+      return true;
+    }
+    i -= nb;
   }
+  return false;
 }
 
 // One block per work item.  Keys only ever decrease, so a plain (possibly
@@ -97,10 +128,10 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(const float *__restrict_
 // the atomic can be skipped when the new key is not smaller.
 __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
                                                          const float *__restrict__ zs, const uint2 *__restrict__ chunks,
-                                                         const uint32_t *__restrict__ counters, SplatCam cam,
-                                                         uint64_t *__restrict__ key) {
-  if (blockIdx.x >= counters[0]) return;
-  const uint2 ch = chunks[blockIdx.x];
+                                                         uint32_t cap, const uint32_t *__restrict__ counters,
+                                                         SplatCam cam, uint64_t *__restrict__ key) {
+  uint2 ch;
+  if (!work_item(blockIdx.x, counters, chunks, cap, &ch)) return;
   const float *P = cam.P;
   // (keeping several points per thread in flight was measured slower: the
   // kernel is bound by the z-buffer atomics, not by load latency)
@@ -127,12 +158,12 @@ __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict
 __global__ __launch_bounds__(kThreads) void soft_accum_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
                                                               const float *__restrict__ zs,
                                                               const uint32_t *__restrict__ rgbx,
-                                                              const uint2 *__restrict__ chunks,
+                                                              const uint2 *__restrict__ chunks, uint32_t cap,
                                                               const uint32_t *__restrict__ counters, SplatCam cam,
                                                               const uint64_t *__restrict__ key, float one_plus_eps,
                                                               uint32_t *__restrict__ acc) {
-  if (blockIdx.x >= counters[0]) return;
-  const uint2 ch = chunks[blockIdx.x];
+  uint2 ch;
+  if (!work_item(blockIdx.x, counters, chunks, cap, &ch)) return;
   const float *P = cam.P;
   for (uint32_t i = threadIdx.x; i < ch.y; i += kThreads) {
     const uint32_t j = ch.x + i;
@@ -213,14 +244,14 @@ hipError_t launch_clear(uint64_t *key, uint32_t npix, uint32_t *counters, hipStr
 hipError_t launch_cull(const CloudDev &c, const CullParams &prm, uint8_t *flags, uint2 *chunks, uint32_t *counters,
                        hipStream_t s) {
   const uint32_t nb = (c.n_cells + kThreads - 1) / kThreads;
-  cull_kernel<<<nb, kThreads, 0, s>>>(c.aabb, c.cell_start, c.n_cells, prm, flags, chunks, counters);
+  cull_kernel<<<nb, kThreads, 0, s>>>(c.aabb, c.cell_start, c.n_cells, prm, flags, chunks, c.max_chunks, counters);
   return hipGetLastError();
 }
 
 hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, const uint32_t *counters, const SplatCam &cam,
                         uint64_t *key, hipStream_t s) {
   if (c.max_chunks == 0) return hipSuccess;
-  splat_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, counters, cam, key);
+  splat_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, c.max_chunks, counters, cam, key);
   return hipGetLastError();
 }
 
@@ -235,8 +266,8 @@ hipError_t launch_soft(const CloudDev &c, const uint2 *chunks, const uint32_t *c
                        uint32_t npix, hipStream_t s) {
   clear_acc_kernel<<<grid_for(npix), kThreads, 0, s>>>(reinterpret_cast<uint4 *>(acc), npix);
   if (c.max_chunks)
-    soft_accum_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, c.rgbx, chunks, counters, cam, key,
-                                                         one_plus_eps, acc);
+    soft_accum_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, c.rgbx, chunks, c.max_chunks, counters, cam,
+                                                         key, one_plus_eps, acc);
   resolve_soft_kernel<<<grid_for(npix), kThreads, 0, s>>>(key, acc, depth, rgba, npix);
   return hipGetLastError();
 }
