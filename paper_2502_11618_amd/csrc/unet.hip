@@ -474,10 +474,10 @@ __global__ __launch_bounds__(256) void head_kernel(const void *__restrict__ x, i
 
 // Tile choice per layer (measured on the 1080p workload).  64-channel
 // workgroups with 2 rows per wave where the layer has a multiple of 64 output
-// channels; in float32, when one image gives fewer than kSmallGrid such
-// workgroups (the 135x240 level of a 1080p frame), 32-channel workgroups
-// double the grid so the last round of workgroups is not nearly empty (the
-// bf16 modes measured no gain from it).  32-channel layers (the first level)
+// channels; in float32 and bf16, when one image gives fewer than kSmallGrid
+// such workgroups (the 135x240 level of a 1080p frame), 32-channel workgroups
+// with 2 rows per wave double the grid so the last round of workgroups is not
+// nearly empty (split bf16 measured no gain from it).  32-channel layers (the first level)
 // use 2 rows per wave, except deep (more than 32 input channels) bf16 layers,
 // where 4 rows measured faster.  Float32 stages 16 channels at a time (32
 // would not leave room for two workgroups per CU), the bf16 modes up to 32;
@@ -509,8 +509,10 @@ hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s)
     return (wide && !small) ? conv_launch<0, 64, 16, 2>(a, cout_pad, s) : conv_launch<0, 32, 16, 2>(a, cout_pad, s);
   } else if constexpr (MODE == 1) {
     if (ck < 16) return hipErrorInvalidValue;
-    if (wide)
+    if (wide && !small)
       return ck == 32 ? conv_launch<1, 64, 32, 2>(a, cout_pad, s) : conv_launch<1, 64, 16, 2>(a, cout_pad, s);
+    if (wide)  // small grid: 32-channel workgroups, 2 rows per wave
+      return ck == 32 ? conv_launch<1, 32, 32, 2>(a, cout_pad, s) : conv_launch<1, 32, 16, 2>(a, cout_pad, s);
     if (a.C0 + a.C1 > 32)
       return ck == 32 ? conv_launch<1, 32, 32, 4>(a, cout_pad, s) : conv_launch<1, 32, 16, 4>(a, cout_pad, s);
     return ck == 32 ? conv_launch<1, 32, 32, 2>(a, cout_pad, s) : conv_launch<1, 32, 16, 2>(a, cout_pad, s);
