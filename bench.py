@@ -197,7 +197,7 @@ def summarize_counters(args):
                 conv_i = 0
             if name.startswith("conv3x3") and name.endswith(", true>"):
                 conv_i = 0  # the first convolution stages the RGBDA image itself
-            if name.startswith("conv3x3") and conv_i is not None and conv_i < len(layer_names):
+            if name.startswith(("conv3x3", "wino3x3")) and conv_i is not None and conv_i < len(layer_names):
                 kname[layer_names[conv_i]] = name
                 name = layer_names[conv_i]
                 conv_i += 1
@@ -525,17 +525,27 @@ def main():
     p0 = precs[0]
     ks = kernel_stats[p0]
     cin0 = 8
-    flops = {name: 2.0 * h * w * co * 9 * ci for (name, h, w, co, ci) in conv_shapes(widths, H, W, cin0)}
+    shapes = conv_shapes(widths, H, W, cin0)
+    flops = {name: 2.0 * h * w * co * 9 * ci for (name, h, w, co, ci) in shapes}
+    # float32 layers past the first run as Winograd F(2x2, 3x3): 16 multiplies
+    # per 2x2 output block and channel pair on the matrix cores (direct: 36)
+    mfma_flops = {name: (2.0 * ((h + 1) // 2) * ((w + 1) // 2) * 16 * co * ci if i > 0 else flops[name])
+                  for i, (name, h, w, co, ci) in enumerate(shapes)}
     conv_ms = {k: v[0] for k, v in ks.items() if k.startswith("conv/")}
     dom = max(conv_ms, key=conv_ms.get)
     achieved = flops[dom] / (conv_ms[dom] * 1e-3) / 1e12
+    executed = mfma_flops[dom] / (conv_ms[dom] * 1e-3) / 1e12
     traffic = recorded_traffic(dom)
     roofline = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["fp32"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp32"], 4),
                 "traffic": None if traffic is None else round(traffic),
-                "flops_per_launch": flops[dom], "avg_launch_ms": round(conv_ms[dom], 4)}
+                "flops_per_launch": flops[dom], "avg_launch_ms": round(conv_ms[dom], 4),
+                "algorithm": "winograd F(2x2,3x3)" if mfma_flops[dom] != flops[dom] else "direct",
+                "mfma_flops_per_launch": mfma_flops[dom], "mfma_achieved": round(executed, 2),
+                "mfma_frac": round(executed / PEAK_TFLOPS["fp32"], 4)}
     unet_ms = sum(v[0] for k, v in ks.items() if k.startswith("conv/") or k in ("pack", "head"))
     unet_flops = sum(flops.values()) + 2.0 * H * W * 3 * widths[0]
+    unet_mfma_flops = sum(mfma_flops.values()) + 2.0 * H * W * 3 * widths[0]
     n_proc = results[p0].get("processed_points_per_frame", proc0)
     gbytes = algorithmic_bytes(H, W, NL, n_proc, filled0, filled0 - kept0)
     geo_names = [k for k in ks if k in gbytes]
@@ -546,7 +556,9 @@ def main():
     rooflines = {
         "unet_fp32_all_convs": {"bound": "mfma", "achieved": round(unet_flops / (unet_ms * 1e-3) / 1e12, 2),
                                 "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
-                                "frac": round(unet_flops / (unet_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4)},
+                                "frac": round(unet_flops / (unet_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4),
+                                "mfma_frac": round(unet_mfma_flops / (unet_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+                                                   4)},
         "render_and_filter": {"bound": "hbm", "achieved": round(geo_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                               "frac": round(geo_gbs / PEAK_HBM_GBS, 4), "bytes_per_frame": geo_bytes,
                               "ms_per_frame": round(geo_ms, 4)},

@@ -908,6 +908,24 @@ lnr_status lnr_unet_load(lnr_context *ctx, const void *blob_host, uint64_t bytes
     cl.bias = static_cast<float *>(bp);
     if (u->prec == Prec::F32) {
       if ((st = upload(packed.data(), 4 * np, &cl.w)) != LNR_OK) return free_all(), st;
+      if (cl.cin_pad % 16 == 0) {
+        // Winograd F(2x2, 3x3) filter transform U = G g G^T, rounded once from
+        // the float64 weights; U[o][4 xi + nu][i]
+        static const double G[4][3] = {{1, 0, 0}, {0.5, 0.5, 0.5}, {0.5, -0.5, 0.5}, {0, 0, 1}};
+        std::vector<float> wu((size_t)cl.cout_pad * 16 * cl.cin_pad, 0.f);
+        for (int o = 0; o < (int)co; ++o)
+          for (int i = 0; i < (int)ci; ++i) {
+            const double *g = &Wd[((size_t)o * ci + i) * 9];
+            for (int xi = 0; xi < 4; ++xi)
+              for (int nu = 0; nu < 4; ++nu) {
+                double acc = 0;
+                for (int dy = 0; dy < 3; ++dy)
+                  for (int dx = 0; dx < 3; ++dx) acc += G[xi][dy] * g[dy * 3 + dx] * G[nu][dx];
+                wu[((size_t)o * 16 + 4 * xi + nu) * cl.cin_pad + i] = (float)acc;
+              }
+          }
+        if ((st = upload(wu.data(), 4 * wu.size(), &cl.wu)) != LNR_OK) return free_all(), st;
+      }
     } else {
       std::vector<uint16_t> hi(np), lo(np);
       for (size_t i = 0; i < np; ++i) {

@@ -114,6 +114,7 @@ struct ConvLayer {
   void *w = nullptr;             // packed weights [cout_pad][k*k][cin_pad] (f32 or bf16 hi)
   void *w_lo = nullptr;          // bf16 low parts (BF16X3)
   float *bias = nullptr;         // [cout_pad]
+  void *wu = nullptr;            // float32 only: Winograd F(2x2,3x3) weights G g G^T [cout_pad][16][cin_pad]
 };
 
 struct ConvCall {

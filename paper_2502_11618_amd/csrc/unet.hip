@@ -48,6 +48,7 @@ struct ConvArgs {
   float *const *head_outs;
   const float *rgbda_depth;
   const uint32_t *rgbda_rgba;
+  const float *wu;  // float32 Winograd-domain weights [cout_pad][16][cin_pad], or null
 };
 
 // 3x3 convolution as implicit GEMM (M = output channels, N = pixels, K = 9 taps
@@ -414,6 +415,301 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   }
 }
 
+// 3x3 convolution in float32 by Winograd's minimal filtering F(2x2, 3x3): each
+// 2x2 block ("tile") of output pixels is Y = A^T [sum_c U_c (.) V_c] A with
+// V_c = B^T d_c B the transform of the tile's 4x4 input patch d_c of channel c
+// and U_c = G g_c G^T the transform of the 3x3 filter (computed on the host);
+//   B^T = [1 0 -1 0; 0 1 1 0; 0 -1 1 0; 0 1 0 -1],
+//   G   = [1 0 0; 1/2 1/2 1/2; 1/2 -1/2 1/2; 0 0 1],
+//   A^T = [1 1 1 0; 0 1 -1 -1].
+// The channel sum is, for each of the 16 transform positions (xi, nu), a GEMM
+// (output channels x tiles, K = input channels) on v_mfma_f32_32x32x2_f32:
+// 16 multiplies per tile and channel pair instead of 36 for the direct form.
+// Workgroup: 8 rows x 32 columns of output pixels (4 x 16 tiles) x 32 output
+// channels, 8 waves; wave w owns transform row xi = w & 3 of tile rows
+// 2 (w >> 2) and 2 (w >> 2) + 1 (32 tiles, one per lane column) and holds the
+// four accumulators (xi, nu = 0..3).  Row xi of B^T d combines two patch rows,
+// so a wave reads 8 of the 16 patch pixels and transforms in registers.
+// The input tile with its halo and the chunk's U (one copy per workgroup) are
+// staged through two LDS buffers, so one barrier per chunk of 16 channels
+// suffices.  Epilogue: each wave reduces its row by A (2 values per tile and
+// channel) into LDS, and every thread then finishes 4 channels of one tile:
+// the A^T row reduction, bias, ReLU, the 2x2 output block (which is also the
+// max-pool window) and the fused 1x1 head.
+template <bool HEAD>
+__global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a) {
+  constexpr int TB = 2, NT = 512;                    // tile blocks (2 tile rows each), threads
+  constexpr int CK = 16;                             // staged channels
+  constexpr int TH = 4 * TB, TW = 32, LW = TW + 2, LPix = (TH + 2) * LW;
+  // input tile in LDS, in 16-byte units (4 channels): unit of (row, col, vector v)
+  // = v PX + (col & 1) PY + row HZ + (col >> 1).  Lanes read the pixels of 16
+  // consecutive tiles, 2 columns apart: with even and odd columns in separate
+  // planes those are 16 consecutive units, one per bank group.
+  constexpr int HZ = LW / 2, PY = (TH + 2) * HZ, PX = 2 * PY;
+  constexpr int CS = 16 * CK + 4;                    // LDS floats per output channel of U (+4: bank spread)
+  constexpr int INP = 4 * PX * 4, BUF = INP + 32 * CS;
+  constexpr int PP = NT / (CK / 4);                  // pixels / weight rows per staging pass (4 vectors each)
+  constexpr int NIN = (LPix + PP - 1) / PP, NWR = 32 * 16 / PP;
+  constexpr int ES = 2 * 32 + 4;                     // epilogue floats per tile: 2 columns x 32 channels (+4)
+  constexpr int EPL = TB * 4 * 32 * ES;
+  __shared__ __attribute__((aligned(16))) float smem[2 * BUF > EPL ? 2 * BUF : EPL];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = lane & 31, h = lane >> 5;
+  const int xi = wv & 3, tb = wv >> 2;
+  const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
+  const int nzc = gridDim.z / a.batch;
+  const int bimg = blockIdx.z / nzc;
+  const int co0 = (blockIdx.z - bimg * nzc) * 32;
+  const int H = a.H, W = a.W;
+  const int Cin = a.C0 + a.C1;
+  const float *in0 = static_cast<const float *>(a.in0) + (size_t)bimg * a.in0_bs;
+  const float *in1 = a.in1 ? static_cast<const float *>(a.in1) + (size_t)bimg * a.in1_bs : nullptr;
+  float *out = a.out ? static_cast<float *>(a.out) + (size_t)bimg * a.out_bs : nullptr;
+  float *out_pool = a.out_pool ? static_cast<float *>(a.out_pool) + (size_t)bimg * a.pool_bs : nullptr;
+  float *head_out = a.head_outs ? a.head_outs[bimg] : (a.head_out ? a.head_out + (size_t)bimg * 3 * H * W : nullptr);
+
+  // staging plan: this thread moves float4 qv of pixels p0, p0 + PP, ... and of
+  // U rows p0, p0 + PP, ... (row r = 16 co + position)
+  const int qv = (tid & 3) * 4, p0 = tid >> 2;
+  int off0[NIN], off1[NIN], lofs[NIN];
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) {
+    const int pix = p0 + k * PP, row = pix / LW, col = pix % LW;
+    const int gy = ty0 - 1 + row, gx = tx0 - 1 + col;
+    const bool inside = pix < LPix && gy >= 0 && gy < H && gx >= 0 && gx < W;
+    off0[k] = inside ? gy * W + gx : -1;
+    off1[k] = inside ? (gy >> 1) * (W >> 1) + (gx >> 1) : -1;
+    lofs[k] = 4 * ((qv / 4) * PX + (col & 1) * PY + row * HZ + (col >> 1));
+  }
+  const float *wsrc = a.wu + ((size_t)co0 * 16 + p0) * a.cin_pad + qv;
+  const size_t wstep = (size_t)PP * a.cin_pad;
+  auto fetch_in = [&](int ci, uint4 (&v)[NIN]) {
+    const bool from0 = ci < a.C0;
+    const size_t csrc = from0 ? a.C0 : a.C1;
+    const float *src = (from0 ? in0 + ci : in1 + (ci - a.C0)) + qv;
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      const int o = from0 ? off0[k] : off1[k];
+      const uint4 x = *reinterpret_cast<const uint4 *>(src + (size_t)(o < 0 ? 0 : o) * csrc);
+      v[k] = o < 0 ? make_uint4(0u, 0u, 0u, 0u) : x;
+    }
+  };
+  auto fetch_w = [&](int ci, uint4 (&v)[NWR]) {
+#pragma unroll
+    for (int k = 0; k < NWR; ++k) v[k] = *reinterpret_cast<const uint4 *>(wsrc + k * wstep + ci);
+  };
+  auto store_in = [&](int buf, const uint4 (&v)[NIN]) {
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      if (!((k + 1) * PP <= LPix || p0 + k * PP < LPix)) continue;
+      *reinterpret_cast<uint4 *>(&smem[buf + lofs[k]]) = v[k];
+    }
+  };
+  auto store_w = [&](int buf, const uint4 (&v)[NWR]) {
+#pragma unroll
+    for (int k = 0; k < NWR; ++k) {
+      const int r = p0 + k * PP;
+      *reinterpret_cast<uint4 *>(&smem[buf + INP + (r >> 4) * CS + (r & 15) * CK + qv]) = v[k];
+    }
+  };
+
+  // lane (n, h): tile (tr, tc) of the workgroup, channels 8g + 4h + s of
+  // chunk group g at k-step s.  Row xi of B^T d is patch row ra + sg * patch row rb.
+  const int tr = 2 * tb + (n >> 4), tc = n & 15;
+  const int ra = xi == 0 ? 0 : (xi == 2 ? 2 : 1);
+  const int rb = xi == 0 ? 2 : (xi == 1 ? 2 : (xi == 2 ? 1 : 3));
+  const float sg = xi == 1 ? 1.f : -1.f;
+  const int ioa = 4 * (h * PX + (2 * tr + ra) * HZ + tc);
+  const int iob = 4 * (h * PX + (2 * tr + rb) * HZ + tc);
+  const int iow = INP + n * CS + 4 * xi * CK + 4 * h;
+  floatx16 acc[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[v][q] = 0.f;
+  auto compute = [&](int buf) {
+    const float *pa = smem + buf + ioa, *pb = smem + buf + iob, *pu = smem + buf + iow;
+#pragma unroll 1
+    for (int g = 0; g < CK / 8; ++g) {
+      float4 da[4], db[4], u[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        // column 2 tc + j of vector 2 g + h
+        const int o = 4 * (2 * g * PX + (j & 1) * PY + (j >> 1));
+        da[j] = *reinterpret_cast<const float4 *>(pa + o);
+        db[j] = *reinterpret_cast<const float4 *>(pb + o);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) u[v] = *reinterpret_cast<const float4 *>(pu + v * CK + 8 * g);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        auto comp = [s](const float4 &f) { return s == 0 ? f.x : (s == 1 ? f.y : (s == 2 ? f.z : f.w)); };
+        float r[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r[j] = fmaf(sg, comp(db[j]), comp(da[j]));
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(u[0]), r[0] - r[2], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(u[1]), r[1] + r[2], acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(u[2]), r[2] - r[1], acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(u[3]), r[1] - r[3], acc[3], 0, 0, 0);
+      }
+    }
+  };
+
+
+  // Chunk c is multiplied from LDS buffer c & 1.  Meanwhile chunk c + 1's U
+  // (mostly L2 hits) and chunk c + 2's input (from HBM) are fetched into
+  // registers, and chunk c + 1 (its input fetched one step earlier) is written
+  // to the other buffer, which every wave finished reading before the previous
+  // barrier.  The U loads are issued first, so waiting for them does not wait
+  // for the younger input loads.
+  const int nch = Cin / CK;
+  uint4 inA[NIN], inB[NIN];
+  {
+    uint4 w[NWR];
+    fetch_in(0, inA);
+    fetch_w(0, w);
+    store_in(0, inA);
+    store_w(0, w);
+  }
+  if (nch > 1) fetch_in(CK, inA);
+  __syncthreads();
+  auto step = [&](int c, uint4 (&nxt)[NIN], uint4 (&nxt2)[NIN]) {
+    const int cur = (c & 1) * BUF;
+    if (c + 1 < nch) {
+      uint4 w[NWR];
+      fetch_w((c + 1) * CK, w);
+      if (c + 2 < nch) fetch_in((c + 2) * CK, nxt2);
+      compute(cur);
+      store_in(BUF - cur, nxt);
+      store_w(BUF - cur, w);
+    } else {
+      compute(cur);
+    }
+    __syncthreads();
+  };
+  for (int c = 0; c < nch; c += 2) {
+    step(c, inA, inB);
+    if (c + 1 < nch) step(c + 1, inB, inA);
+  }
+
+  // ---- epilogue.  Accumulator register 4j + i of (xi, nu) holds position
+  // (xi, nu) of channel co0 + 8j + 4h + i for tile n; reduce nu by A.
+  float *E = smem;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float4 p0v, p1v;
+    p0v.x = acc[0][4 * j + 0] + acc[1][4 * j + 0] + acc[2][4 * j + 0];
+    p0v.y = acc[0][4 * j + 1] + acc[1][4 * j + 1] + acc[2][4 * j + 1];
+    p0v.z = acc[0][4 * j + 2] + acc[1][4 * j + 2] + acc[2][4 * j + 2];
+    p0v.w = acc[0][4 * j + 3] + acc[1][4 * j + 3] + acc[2][4 * j + 3];
+    p1v.x = acc[1][4 * j + 0] - acc[2][4 * j + 0] - acc[3][4 * j + 0];
+    p1v.y = acc[1][4 * j + 1] - acc[2][4 * j + 1] - acc[3][4 * j + 1];
+    p1v.z = acc[1][4 * j + 2] - acc[2][4 * j + 2] - acc[3][4 * j + 2];
+    p1v.w = acc[1][4 * j + 3] - acc[2][4 * j + 3] - acc[3][4 * j + 3];
+    float *e = E + ((tb * 4 + xi) * 32 + n) * ES + 8 * j + 4 * h;
+    *reinterpret_cast<float4 *>(e) = p0v;
+    *reinterpret_cast<float4 *>(e + 32) = p1v;
+  }
+  __syncthreads();
+  // thread: channels c .. c + 3 of workgroup tile et; reduce xi by A^T
+  const int q = tid & 7, et = tid >> 3, etb = et >> 5, en = et & 31;
+  const int gy0 = ty0 + 2 * (2 * etb + (en >> 4)), gx0 = tx0 + 2 * (en & 15);
+  const int c = co0 + 4 * q;
+  float y[2][2][4];  // [row][column][channel]
+#pragma unroll
+  for (int col = 0; col < 2; ++col) {
+    float4 P[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+      P[x] = *reinterpret_cast<const float4 *>(E + ((etb * 4 + x) * 32 + en) * ES + col * 32 + 4 * q);
+    y[0][col][0] = P[0].x + P[1].x + P[2].x;
+    y[0][col][1] = P[0].y + P[1].y + P[2].y;
+    y[0][col][2] = P[0].z + P[1].z + P[2].z;
+    y[0][col][3] = P[0].w + P[1].w + P[2].w;
+    y[1][col][0] = P[1].x - P[2].x - P[3].x;
+    y[1][col][1] = P[1].y - P[2].y - P[3].y;
+    y[1][col][2] = P[1].z - P[2].z - P[3].z;
+    y[1][col][3] = P[1].w - P[2].w - P[3].w;
+  }
+  const bool live = c < a.cout;
+  float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (live) b = *reinterpret_cast<const float4 *>(a.bias + c);
+  const float bb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int col = 0; col < 2; ++col)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) y[r][col][i] = fmaxf(y[r][col][i] + bb[i], 0.f);
+  if constexpr (HEAD) {
+    // the workgroup holds every output channel (cout <= 32): 1x1 head summed
+    // over the 8 threads of the tile
+    float hs[2][2][3];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int col = 0; col < 2; ++col) {
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        if (live) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            s0 = fmaf(a.head_w[c + i], y[r][col][i], s0);
+            s1 = fmaf(a.head_w[a.cout + c + i], y[r][col][i], s1);
+            s2 = fmaf(a.head_w[2 * a.cout + c + i], y[r][col][i], s2);
+          }
+        }
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1) {
+          s0 += __shfl_xor(s0, m, 64);
+          s1 += __shfl_xor(s1, m, 64);
+          s2 += __shfl_xor(s2, m, 64);
+        }
+        hs[r][col][0] = s0;
+        hs[r][col][1] = s1;
+        hs[r][col][2] = s2;
+      }
+    if (q < 4) {
+      // thread q writes pixel (q >> 1, q & 1) of the block
+      const int r = q >> 1, col = q & 1, gy = gy0 + r, gx = gx0 + col;
+      float o0 = hs[0][0][0], o1 = hs[0][0][1], o2 = hs[0][0][2];
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+          if (rr == r && cc == col) {
+            o0 = hs[rr][cc][0];
+            o1 = hs[rr][cc][1];
+            o2 = hs[rr][cc][2];
+          }
+      if (gy < H && gx < W) {
+        const size_t HW = (size_t)H * W, p = (size_t)gy * W + gx;
+        head_out[p] = o0 + a.head_b[0];
+        head_out[HW + p] = o1 + a.head_b[1];
+        head_out[2 * HW + p] = o2 + a.head_b[2];
+      }
+    }
+    return;
+  }
+  if (!live) return;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int col = 0; col < 2; ++col) {
+      const int gy = gy0 + r, gx = gx0 + col;
+      if (gy < H && gx < W)
+        *reinterpret_cast<float4 *>(out + ((size_t)gy * W + gx) * a.cout + c) =
+            make_float4(y[r][col][0], y[r][col][1], y[r][col][2], y[r][col][3]);
+    }
+  if (out_pool && gy0 < H && gx0 < W) {
+    float m[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = fmaxf(fmaxf(y[0][0][i], y[0][1][i]), fmaxf(y[1][0][i], y[1][1][i]));
+    *reinterpret_cast<float4 *>(out_pool + ((size_t)(gy0 >> 1) * (W >> 1) + (gx0 >> 1)) * a.cout + c) =
+        make_float4(m[0], m[1], m[2], m[3]);
+  }
+}
+
 // RGBDA -> network input x = (r/255, g/255, b/255, A ? D/16 : 0, A, 0...), cpad channels
 template <int MODE>
 __global__ __launch_bounds__(256) void pack_kernel(const float *__restrict__ depth, const uint32_t *__restrict__ rgba,
@@ -477,7 +773,8 @@ __global__ __launch_bounds__(256) void head_kernel(const void *__restrict__ x, i
 // channels; in float32 and bf16, when one image gives fewer than kSmallGrid
 // such workgroups (the 135x240 level of a 1080p frame), 32-channel workgroups
 // with 2 rows per wave double the grid so the last round of workgroups is not
-// nearly empty (split bf16 measured no gain from it).  32-channel layers (the first level)
+// nearly empty (split bf16 measured no gain from it; a layer with the fused
+// head keeps all its channels in one workgroup).  32-channel layers (the first level)
 // use 2 rows per wave, except deep (more than 32 input channels) bf16 layers,
 // where 4 rows measured faster.  Float32 stages 16 channels at a time (32
 // would not leave room for two workgroups per CU), the bf16 modes up to 32;
@@ -500,10 +797,24 @@ hipError_t conv_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
   return hipGetLastError();
 }
 
+// float32 layers whose inputs come in chunks of 16 channels (all but the
+// first) run as Winograd F(2x2, 3x3); 8 x 32 pixel tiles of 32 output channels
+hipError_t wino_launch(const ConvArgs &a, int cout_pad, bool head, hipStream_t s) {
+  dim3 grid((a.W + 31) / 32, (a.H + 7) / 8, (cout_pad / 32) * a.batch);
+  if (head)
+    wino3x3_kernel<true><<<grid, 512, 0, s>>>(a);
+  else
+    wino3x3_kernel<false><<<grid, 512, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 template <int MODE>
 hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s) {
   const bool wide = cout_pad % 64 == 0;
-  const bool small = (long)((a.W + 31) / 32) * ((a.H + 7) / 8) * (cout_pad / 64) < kSmallGrid;
+  // a fused head sums over every output channel in one workgroup: no 32-channel
+  // split of a 64-channel layer then
+  const bool head = a.head_out || a.head_outs;
+  const bool small = !head && (long)((a.W + 31) / 32) * ((a.H + 7) / 8) * (cout_pad / 64) < kSmallGrid;
   if constexpr (MODE == 0) {
     if (ck == 8) return wide ? conv_launch<0, 64, 8, 2>(a, cout_pad, s) : conv_launch<0, 32, 8, 2>(a, cout_pad, s);
     return (wide && !small) ? conv_launch<0, 64, 16, 2>(a, cout_pad, s) : conv_launch<0, 32, 16, 2>(a, cout_pad, s);
@@ -540,13 +851,17 @@ hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s) {
   const ConvLayer &L = *c.layer;
   ConvArgs a{c.in0, c.in1, c.C0, c.C1, c.H, c.W, L.w, L.w_lo, L.bias, L.cout, L.cin_pad, c.out, c.out_pool,
              c.head_w, c.head_b, c.head_out, c.batch < 1 ? 1 : c.batch, c.in0_bs, c.in1_bs, c.out_bs, c.pool_bs,
-             c.head_outs, c.rgbda_depth, c.rgbda_rgba};
-  if (c.head_out && (L.cout_pad > 64 || c.out_pool)) return hipErrorInvalidValue;
+             c.head_outs, c.rgbda_depth, c.rgbda_rgba, static_cast<const float *>(L.wu)};
+  const bool head = c.head_out || c.head_outs;
+  if (head && (L.cout_pad > 64 || c.out_pool)) return hipErrorInvalidValue;
   if (c.rgbda_depth && (!c.rgbda_rgba || c.C1 != 0 || c.batch > 1)) return hipErrorInvalidValue;
   const int step = (p == Prec::F32) ? 8 : 16;
   int ck = 32;
   while (ck > step && ((c.C0 % ck) != 0 || (c.C1 % ck) != 0)) ck >>= 1;
   if ((c.C0 % ck) != 0 || (c.C1 % ck) != 0 || (c.C0 + c.C1) != L.cin_pad) return hipErrorInvalidValue;
+  if (p == Prec::F32 && L.wu && !c.rgbda_depth && c.C0 % 16 == 0 && c.C1 % 16 == 0 &&
+      (!head || L.cout_pad == 32))
+    return wino_launch(a, L.cout_pad, head, s);
   switch (p) {
     case Prec::F32: return conv_dispatch<0>(a, ck, L.cout_pad, s);
     case Prec::BF16: return conv_dispatch<1>(a, ck, L.cout_pad, s);

@@ -46,6 +46,8 @@ def _random_rgbda(rng, H, W):
     ((16, 32, 64), 64, 64, "zero"),
     ((32, 64, 128, 256), 72, 112, "uniform"),
     ((16, 32, 48, 64, 80), 48, 80, "uniform"),
+    # 64 channels at full resolution: the fused head spans two 32-channel tiles
+    ((64, 96), 24, 48, "uniform"),
 ])
 def test_unet_random_images(lnr, ctx, prec, widths, H, W, bias):
     blob = synth.make_unet_blob(widths, seed=len(widths), bias=bias)
