@@ -17,6 +17,8 @@
 //          hi*hi + hi*lo + lo*hi on the bf16 MFMA with float32 accumulation.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "lnr_internal.h"
 
 namespace lnr {
@@ -436,10 +438,11 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 // channel) into LDS, and every thread then finishes 4 channels of one tile:
 // the A^T row reduction, bias, ReLU, the 2x2 output block (which is also the
 // max-pool window) and the fused 1x1 head.
-template <bool HEAD>
-__global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a) {
-  constexpr int TB = 2, NT = 512;                    // tile blocks (2 tile rows each), threads
-  constexpr int CK = 16;                             // staged channels
+template <bool HEAD, int MB, int CK>
+__global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a, int ntx, int nty, int nzc, int ntiles) {
+  constexpr int NT = 512, TB = 2;                    // threads; tile blocks of 2 tile rows
+  constexpr int NCO = 32 * MB;                       // output channels per workgroup tile
+  constexpr int NV = CK / 4;                         // staged channels CK: 16-byte vectors per pixel
   constexpr int TH = 4 * TB, TW = 32, LW = TW + 2, LPix = (TH + 2) * LW;
   // input tile in LDS, in 16-byte units (4 channels): unit of (row, col, vector v)
   // = v PX + (col & 1) PY + row HZ + (col >> 1).  Lanes read the pixels of 16
@@ -447,47 +450,84 @@ __global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a) {
   // planes those are 16 consecutive units, one per bank group.
   constexpr int HZ = LW / 2, PY = (TH + 2) * HZ, PX = 2 * PY;
   constexpr int CS = 16 * CK + 4;                    // LDS floats per output channel of U (+4: bank spread)
-  constexpr int INP = 4 * PX * 4, BUF = INP + 32 * CS;
-  constexpr int PP = NT / (CK / 4);                  // pixels / weight rows per staging pass (4 vectors each)
-  constexpr int NIN = (LPix + PP - 1) / PP, NWR = 32 * 16 / PP;
+  constexpr int INP = NV * PX * 4, BUF = INP + NCO * CS;
+  constexpr int PP = NT / NV;                        // pixels / U rows per staging pass
+  constexpr int NIN = (LPix + PP - 1) / PP, NWR = NCO * 16 / PP;
   constexpr int ES = 2 * 32 + 4;                     // epilogue floats per tile: 2 columns x 32 channels (+4)
   constexpr int EPL = TB * 4 * 32 * ES;
-  __shared__ __attribute__((aligned(16))) float smem[2 * BUF > EPL ? 2 * BUF : EPL];
+  // LDS: [buffer 0][GAP][buffer 1]; the epilogue's EPL floats start at the
+  // buffer just finished (0 or BUF) and may run into the gap
+  constexpr int GAP = EPL > BUF ? EPL - BUF : 0, B1 = BUF + GAP;
+  static_assert(NCO * 16 % PP == 0, "U rows must fill whole staging passes");
+  __shared__ __attribute__((aligned(16))) float smem[2 * BUF + GAP];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = lane & 31, h = lane >> 5;
   const int xi = wv & 3, tb = wv >> 2;
-  const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
-  const int nzc = gridDim.z / a.batch;
-  const int bimg = blockIdx.z / nzc;
-  const int co0 = (blockIdx.z - bimg * nzc) * 32;
   const int H = a.H, W = a.W;
   const int Cin = a.C0 + a.C1;
-  const float *in0 = static_cast<const float *>(a.in0) + (size_t)bimg * a.in0_bs;
-  const float *in1 = a.in1 ? static_cast<const float *>(a.in1) + (size_t)bimg * a.in1_bs : nullptr;
-  float *out = a.out ? static_cast<float *>(a.out) + (size_t)bimg * a.out_bs : nullptr;
-  float *out_pool = a.out_pool ? static_cast<float *>(a.out_pool) + (size_t)bimg * a.pool_bs : nullptr;
-  float *head_out = a.head_outs ? a.head_outs[bimg] : (a.head_out ? a.head_out + (size_t)bimg * 3 * H * W : nullptr);
+
+  // Persistent workgroups walk a list of tiles (an 8 x 32 pixel block of one
+  // image and one block of NCO output channels).  Tile order: output-channel
+  // blocks of one pixel block are consecutive, then pixel blocks, then images;
+  // with a grid of 8k workgroups, workgroup w (on XCD w mod 8) walks every
+  // k-th tile of the w mod 8 -th eighth of the list, so tiles that share input
+  // pixels run on the same XCD at about the same time.
+  const int G = gridDim.x;
+  int t_first, t_end, t_step;
+  if (G % 8 == 0 && G < ntiles) {
+    const int x = blockIdx.x & 7, per = G >> 3;
+    t_first = (int)((long)x * ntiles / 8) + (blockIdx.x >> 3);
+    t_end = (int)((long)(x + 1) * ntiles / 8);
+    t_step = per;
+  } else {
+    t_first = blockIdx.x;
+    t_end = ntiles;
+    t_step = G;
+  }
+  struct TileId { int ty0, tx0, co0, bimg; };
+  auto decode = [&](int T) {
+    TileId d;
+    const int cz = T % nzc, sp = T / nzc;
+    const int nsp = ntx * nty;
+    d.bimg = sp / nsp;
+    const int r = sp - d.bimg * nsp;
+    d.ty0 = (r / ntx) * TH;
+    d.tx0 = (r % ntx) * TW;
+    d.co0 = cz * NCO;
+    return d;
+  };
 
   // staging plan: this thread moves float4 qv of pixels p0, p0 + PP, ... and of
   // U rows p0, p0 + PP, ... (row r = 16 co + position)
-  const int qv = (tid & 3) * 4, p0 = tid >> 2;
-  int off0[NIN], off1[NIN], lofs[NIN];
+  const int qv = (tid % NV) * 4, p0 = tid / NV;
+  int lofs[NIN];
 #pragma unroll
   for (int k = 0; k < NIN; ++k) {
     const int pix = p0 + k * PP, row = pix / LW, col = pix % LW;
-    const int gy = ty0 - 1 + row, gx = tx0 - 1 + col;
-    const bool inside = pix < LPix && gy >= 0 && gy < H && gx >= 0 && gx < W;
-    off0[k] = inside ? gy * W + gx : -1;
-    off1[k] = inside ? (gy >> 1) * (W >> 1) + (gx >> 1) : -1;
     lofs[k] = 4 * ((qv / 4) * PX + (col & 1) * PY + row * HZ + (col >> 1));
   }
-  const float *wsrc = a.wu + ((size_t)co0 * 16 + p0) * a.cin_pad + qv;
+  // fetch state: the tile whose chunks are being fetched
+  int off0[NIN], off1[NIN];
+  const float *fin0 = nullptr, *fin1 = nullptr, *wsrc = nullptr;
+  auto set_fetch_tile = [&](const TileId &d) {
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      const int pix = p0 + k * PP, row = pix / LW, col = pix % LW;
+      const int gy = d.ty0 - 1 + row, gx = d.tx0 - 1 + col;
+      const bool inside = pix < LPix && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      off0[k] = inside ? gy * W + gx : -1;
+      off1[k] = inside ? (gy >> 1) * (W >> 1) + (gx >> 1) : -1;
+    }
+    fin0 = static_cast<const float *>(a.in0) + (size_t)d.bimg * a.in0_bs;
+    fin1 = a.in1 ? static_cast<const float *>(a.in1) + (size_t)d.bimg * a.in1_bs : nullptr;
+    wsrc = a.wu + ((size_t)d.co0 * 16 + p0) * a.cin_pad + qv;
+  };
   const size_t wstep = (size_t)PP * a.cin_pad;
   auto fetch_in = [&](int ci, uint4 (&v)[NIN]) {
     const bool from0 = ci < a.C0;
     const size_t csrc = from0 ? a.C0 : a.C1;
-    const float *src = (from0 ? in0 + ci : in1 + (ci - a.C0)) + qv;
+    const float *src = (from0 ? fin0 + ci : fin1 + (ci - a.C0)) + qv;
 #pragma unroll
     for (int k = 0; k < NIN; ++k) {
       const int o = from0 ? off0[k] : off1[k];
@@ -523,16 +563,21 @@ __global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a) {
   const int ioa = 4 * (h * PX + (2 * tr + ra) * HZ + tc);
   const int iob = 4 * (h * PX + (2 * tr + rb) * HZ + tc);
   const int iow = INP + n * CS + 4 * xi * CK + 4 * h;
-  floatx16 acc[4];
+  // acc[mb][nu]: positions (xi, nu) of output channels co0 + 32 mb + ... of 32 tiles
+  floatx16 acc[MB][4];
+  auto zero_acc = [&]() {
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[v][q] = 0.f;
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[mb][v][q] = 0.f;
+  };
   auto compute = [&](int buf) {
     const float *pa = smem + buf + ioa, *pb = smem + buf + iob, *pu = smem + buf + iow;
 #pragma unroll 1
     for (int g = 0; g < CK / 8; ++g) {
-      float4 da[4], db[4], u[4];
+      float4 da[4], db[4], u[MB][4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         // column 2 tc + j of vector 2 g + h
@@ -541,172 +586,214 @@ __global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a) {
         db[j] = *reinterpret_cast<const float4 *>(pb + o);
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) u[v] = *reinterpret_cast<const float4 *>(pu + v * CK + 8 * g);
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) u[mb][v] = *reinterpret_cast<const float4 *>(pu + mb * 32 * CS + v * CK + 8 * g);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         auto comp = [s](const float4 &f) { return s == 0 ? f.x : (s == 1 ? f.y : (s == 2 ? f.z : f.w)); };
         float r[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) r[j] = fmaf(sg, comp(db[j]), comp(da[j]));
-        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(u[0]), r[0] - r[2], acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(u[1]), r[1] + r[2], acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(u[2]), r[2] - r[1], acc[2], 0, 0, 0);
-        acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(u[3]), r[1] - r[3], acc[3], 0, 0, 0);
+        const float t[4] = {r[0] - r[2], r[1] + r[2], r[2] - r[1], r[1] - r[3]};
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[mb][v] = __builtin_amdgcn_mfma_f32_32x32x2f32(comp(u[mb][v]), t[v], acc[mb][v], 0, 0, 0);
       }
     }
   };
 
-
-  // Chunk c is multiplied from LDS buffer c & 1.  Meanwhile chunk c + 1's U
-  // (mostly L2 hits) and chunk c + 2's input (from HBM) are fetched into
-  // registers, and chunk c + 1 (its input fetched one step earlier) is written
-  // to the other buffer, which every wave finished reading before the previous
-  // barrier.  The U loads are issued first, so waiting for them does not wait
-  // for the younger input loads.
-  const int nch = Cin / CK;
-  uint4 inA[NIN], inB[NIN];
-  {
-    uint4 w[NWR];
-    fetch_in(0, inA);
-    fetch_w(0, w);
-    store_in(0, inA);
-    store_w(0, w);
-  }
-  if (nch > 1) fetch_in(CK, inA);
-  __syncthreads();
-  auto step = [&](int c, uint4 (&nxt)[NIN], uint4 (&nxt2)[NIN]) {
-    const int cur = (c & 1) * BUF;
-    if (c + 1 < nch) {
-      uint4 w[NWR];
-      fetch_w((c + 1) * CK, w);
-      if (c + 2 < nch) fetch_in((c + 2) * CK, nxt2);
-      compute(cur);
-      store_in(BUF - cur, nxt);
-      store_w(BUF - cur, w);
-    } else {
-      compute(cur);
-    }
-    __syncthreads();
-  };
-  for (int c = 0; c < nch; c += 2) {
-    step(c, inA, inB);
-    if (c + 1 < nch) step(c + 1, inB, inA);
-  }
-
-  // ---- epilogue.  Accumulator register 4j + i of (xi, nu) holds position
-  // (xi, nu) of channel co0 + 8j + 4h + i for tile n; reduce nu by A.
-  float *E = smem;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    float4 p0v, p1v;
-    p0v.x = acc[0][4 * j + 0] + acc[1][4 * j + 0] + acc[2][4 * j + 0];
-    p0v.y = acc[0][4 * j + 1] + acc[1][4 * j + 1] + acc[2][4 * j + 1];
-    p0v.z = acc[0][4 * j + 2] + acc[1][4 * j + 2] + acc[2][4 * j + 2];
-    p0v.w = acc[0][4 * j + 3] + acc[1][4 * j + 3] + acc[2][4 * j + 3];
-    p1v.x = acc[1][4 * j + 0] - acc[2][4 * j + 0] - acc[3][4 * j + 0];
-    p1v.y = acc[1][4 * j + 1] - acc[2][4 * j + 1] - acc[3][4 * j + 1];
-    p1v.z = acc[1][4 * j + 2] - acc[2][4 * j + 2] - acc[3][4 * j + 2];
-    p1v.w = acc[1][4 * j + 3] - acc[2][4 * j + 3] - acc[3][4 * j + 3];
-    float *e = E + ((tb * 4 + xi) * 32 + n) * ES + 8 * j + 4 * h;
-    *reinterpret_cast<float4 *>(e) = p0v;
-    *reinterpret_cast<float4 *>(e + 32) = p1v;
-  }
-  __syncthreads();
-  // thread: channels c .. c + 3 of workgroup tile et; reduce xi by A^T
+  // ---- epilogue of one tile into E (EPL floats of LDS nobody reads any
+  // more), one block of 32 output channels at a time.  Accumulator register
+  // 4j + i of acc[mb][nu] holds position (xi, nu) of channel co0 + 32 mb +
+  // 8j + 4h + i for tile n; each wave reduces nu by A into E, then thread
+  // (tile et, quad q) reduces xi by A^T for channels c .. c + 3.
   const int q = tid & 7, et = tid >> 3, etb = et >> 5, en = et & 31;
-  const int gy0 = ty0 + 2 * (2 * etb + (en >> 4)), gx0 = tx0 + 2 * (en & 15);
-  const int c = co0 + 4 * q;
-  float y[2][2][4];  // [row][column][channel]
-#pragma unroll
-  for (int col = 0; col < 2; ++col) {
-    float4 P[4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-      P[x] = *reinterpret_cast<const float4 *>(E + ((etb * 4 + x) * 32 + en) * ES + col * 32 + 4 * q);
-    y[0][col][0] = P[0].x + P[1].x + P[2].x;
-    y[0][col][1] = P[0].y + P[1].y + P[2].y;
-    y[0][col][2] = P[0].z + P[1].z + P[2].z;
-    y[0][col][3] = P[0].w + P[1].w + P[2].w;
-    y[1][col][0] = P[1].x - P[2].x - P[3].x;
-    y[1][col][1] = P[1].y - P[2].y - P[3].y;
-    y[1][col][2] = P[1].z - P[2].z - P[3].z;
-    y[1][col][3] = P[1].w - P[2].w - P[3].w;
-  }
-  const bool live = c < a.cout;
-  float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (live) b = *reinterpret_cast<const float4 *>(a.bias + c);
-  const float bb[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int col = 0; col < 2; ++col)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) y[r][col][i] = fmaxf(y[r][col][i] + bb[i], 0.f);
-  if constexpr (HEAD) {
-    // the workgroup holds every output channel (cout <= 32): 1x1 head summed
-    // over the 8 threads of the tile
-    float hs[2][2][3];
+  auto epilogue = [&](float *E, const TileId &d) {
+    const int gy0 = d.ty0 + 2 * (2 * etb + (en >> 4)), gx0 = d.tx0 + 2 * (en & 15);
+    float *out = a.out ? static_cast<float *>(a.out) + (size_t)d.bimg * a.out_bs : nullptr;
+    float *out_pool = a.out_pool ? static_cast<float *>(a.out_pool) + (size_t)d.bimg * a.pool_bs : nullptr;
+    float hs[2][2][3];  // head partial sums of this thread's channels
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
+      for (int col = 0; col < 2; ++col) hs[r][col][0] = hs[r][col][1] = hs[r][col][2] = 0.f;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      if (mb > 0) __syncthreads();  // the previous block's readers are done with E
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float4 p0v, p1v;
+        p0v.x = acc[mb][0][4 * j + 0] + acc[mb][1][4 * j + 0] + acc[mb][2][4 * j + 0];
+        p0v.y = acc[mb][0][4 * j + 1] + acc[mb][1][4 * j + 1] + acc[mb][2][4 * j + 1];
+        p0v.z = acc[mb][0][4 * j + 2] + acc[mb][1][4 * j + 2] + acc[mb][2][4 * j + 2];
+        p0v.w = acc[mb][0][4 * j + 3] + acc[mb][1][4 * j + 3] + acc[mb][2][4 * j + 3];
+        p1v.x = acc[mb][1][4 * j + 0] - acc[mb][2][4 * j + 0] - acc[mb][3][4 * j + 0];
+        p1v.y = acc[mb][1][4 * j + 1] - acc[mb][2][4 * j + 1] - acc[mb][3][4 * j + 1];
+        p1v.z = acc[mb][1][4 * j + 2] - acc[mb][2][4 * j + 2] - acc[mb][3][4 * j + 2];
+        p1v.w = acc[mb][1][4 * j + 3] - acc[mb][2][4 * j + 3] - acc[mb][3][4 * j + 3];
+        float *e = E + ((tb * 4 + xi) * 32 + n) * ES + 8 * j + 4 * h;
+        *reinterpret_cast<float4 *>(e) = p0v;
+        *reinterpret_cast<float4 *>(e + 32) = p1v;
+      }
+      __syncthreads();
+      const int c = d.co0 + 32 * mb + 4 * q;
+      float y[2][2][4];  // [row][column][channel]
+#pragma unroll
       for (int col = 0; col < 2; ++col) {
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        float4 P[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+          P[x] = *reinterpret_cast<const float4 *>(E + ((etb * 4 + x) * 32 + en) * ES + col * 32 + 4 * q);
+        y[0][col][0] = P[0].x + P[1].x + P[2].x;
+        y[0][col][1] = P[0].y + P[1].y + P[2].y;
+        y[0][col][2] = P[0].z + P[1].z + P[2].z;
+        y[0][col][3] = P[0].w + P[1].w + P[2].w;
+        y[1][col][0] = P[1].x - P[2].x - P[3].x;
+        y[1][col][1] = P[1].y - P[2].y - P[3].y;
+        y[1][col][2] = P[1].z - P[2].z - P[3].z;
+        y[1][col][3] = P[1].w - P[2].w - P[3].w;
+      }
+      const bool live = c < a.cout;
+      float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (live) b = *reinterpret_cast<const float4 *>(a.bias + c);
+      const float bb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int col = 0; col < 2; ++col)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) y[r][col][i] = fmaxf(y[r][col][i] + bb[i], 0.f);
+      if constexpr (HEAD) {
         if (live) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            s0 = fmaf(a.head_w[c + i], y[r][col][i], s0);
-            s1 = fmaf(a.head_w[a.cout + c + i], y[r][col][i], s1);
-            s2 = fmaf(a.head_w[2 * a.cout + c + i], y[r][col][i], s2);
-          }
+          for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int col = 0; col < 2; ++col)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                hs[r][col][0] = fmaf(a.head_w[c + i], y[r][col][i], hs[r][col][0]);
+                hs[r][col][1] = fmaf(a.head_w[a.cout + c + i], y[r][col][i], hs[r][col][1]);
+                hs[r][col][2] = fmaf(a.head_w[2 * a.cout + c + i], y[r][col][i], hs[r][col][2]);
+              }
         }
+      } else if (live) {
 #pragma unroll
-        for (int m = 1; m < 8; m <<= 1) {
-          s0 += __shfl_xor(s0, m, 64);
-          s1 += __shfl_xor(s1, m, 64);
-          s2 += __shfl_xor(s2, m, 64);
-        }
-        hs[r][col][0] = s0;
-        hs[r][col][1] = s1;
-        hs[r][col][2] = s2;
-      }
-    if (q < 4) {
-      // thread q writes pixel (q >> 1, q & 1) of the block
-      const int r = q >> 1, col = q & 1, gy = gy0 + r, gx = gx0 + col;
-      float o0 = hs[0][0][0], o1 = hs[0][0][1], o2 = hs[0][0][2];
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int rr = 0; rr < 2; ++rr)
-#pragma unroll
-        for (int cc = 0; cc < 2; ++cc)
-          if (rr == r && cc == col) {
-            o0 = hs[rr][cc][0];
-            o1 = hs[rr][cc][1];
-            o2 = hs[rr][cc][2];
+          for (int col = 0; col < 2; ++col) {
+            const int gy = gy0 + r, gx = gx0 + col;
+            if (gy < H && gx < W)
+              *reinterpret_cast<float4 *>(out + ((size_t)gy * W + gx) * a.cout + c) =
+                  make_float4(y[r][col][0], y[r][col][1], y[r][col][2], y[r][col][3]);
           }
-      if (gy < H && gx < W) {
-        const size_t HW = (size_t)H * W, p = (size_t)gy * W + gx;
-        head_out[p] = o0 + a.head_b[0];
-        head_out[HW + p] = o1 + a.head_b[1];
-        head_out[2 * HW + p] = o2 + a.head_b[2];
+        if (out_pool && gy0 < H && gx0 < W) {
+          float m[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) m[i] = fmaxf(fmaxf(y[0][0][i], y[0][1][i]), fmaxf(y[1][0][i], y[1][1][i]));
+          *reinterpret_cast<float4 *>(out_pool + ((size_t)(gy0 >> 1) * (W >> 1) + (gx0 >> 1)) * a.cout + c) =
+              make_float4(m[0], m[1], m[2], m[3]);
+        }
       }
     }
-    return;
+    if constexpr (HEAD) {
+      // the tile holds every output channel (cout <= NCO): sum the head over
+      // the tile's 8 threads; thread q < 4 writes pixel (q >> 1, q & 1)
+      float *head_out =
+          a.head_outs ? a.head_outs[d.bimg] : (a.head_out ? a.head_out + (size_t)d.bimg * 3 * H * W : nullptr);
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int col = 0; col < 2; ++col)
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int m = 1; m < 8; m <<= 1) hs[r][col][k] += __shfl_xor(hs[r][col][k], m, 64);
+      if (q < 4) {
+        const int r = q >> 1, col = q & 1, gy = gy0 + r, gx = gx0 + col;
+        float o0 = hs[0][0][0], o1 = hs[0][0][1], o2 = hs[0][0][2];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+          for (int cc = 0; cc < 2; ++cc)
+            if (rr == r && cc == col) {
+              o0 = hs[rr][cc][0];
+              o1 = hs[rr][cc][1];
+              o2 = hs[rr][cc][2];
+            }
+        if (gy < H && gx < W) {
+          const size_t HW = (size_t)H * W, p = (size_t)gy * W + gx;
+          head_out[p] = o0 + a.head_b[0];
+          head_out[HW + p] = o1 + a.head_b[1];
+          head_out[2 * HW + p] = o2 + a.head_b[2];
+        }
+      }
+    }
+  };
+
+  // The chunks of this workgroup's tiles form one stream: chunk step t is
+  // multiplied from LDS buffer t & 1 while step t + 1 (the next chunk of the
+  // tile, or the first chunk of the next tile) is fetched into registers; it
+  // is then written to the other buffer, which every wave finished reading
+  // before the previous barrier.  After a tile's last chunk the epilogue runs
+  // on the buffer just finished, so the next tile's first chunk is already
+  // staged when its multiplications start.
+  if (t_first >= t_end) return;
+  const int nch = Cin / CK;
+  TileId cur = decode(t_first);
+  set_fetch_tile(cur);
+  {
+    uint4 v[NIN], w[NWR];
+    fetch_in(0, v);
+    fetch_w(0, w);
+    store_in(0, v);
+    store_w(0, w);
   }
-  if (!live) return;
+  __syncthreads();
+  zero_acc();
+  uint4 v[NIN], w[NWR];
+  int T = t_first, c = 0, buf = 0;
+  for (;;) {
+    const bool last = c + 1 == nch;
+    const int Tn = last ? T + t_step : T;
+    const bool more = Tn < t_end;
+    TileId nxt = cur;
+    if (more) {
+      if (last) {
+        nxt = decode(Tn);
+        set_fetch_tile(nxt);
+      }
+      const int cn = last ? 0 : (c + 1) * CK;
+      fetch_w(cn, w);
+      fetch_in(cn, v);
+    } else {
+      // (defined values on every path keep the arrays in registers)
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < NWR; ++k) w[k] = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-    for (int col = 0; col < 2; ++col) {
-      const int gy = gy0 + r, gx = gx0 + col;
-      if (gy < H && gx < W)
-        *reinterpret_cast<float4 *>(out + ((size_t)gy * W + gx) * a.cout + c) =
-            make_float4(y[r][col][0], y[r][col][1], y[r][col][2], y[r][col][3]);
+      for (int k = 0; k < NIN; ++k) v[k] = make_uint4(0u, 0u, 0u, 0u);
     }
-  if (out_pool && gy0 < H && gx0 < W) {
-    float m[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) m[i] = fmaxf(fmaxf(y[0][0][i], y[0][1][i]), fmaxf(y[1][0][i], y[1][1][i]));
-    *reinterpret_cast<float4 *>(out_pool + ((size_t)(gy0 >> 1) * (W >> 1) + (gx0 >> 1)) * a.cout + c) =
-        make_float4(m[0], m[1], m[2], m[3]);
+    compute(buf);  // one call site: the accumulators stay in place
+    const int other = buf == 0 ? B1 : 0;
+    if (more) {
+      store_in(other, v);
+      store_w(other, w);
+    }
+    __syncthreads();
+    if (last) {
+      epilogue(smem + (buf == 0 ? 0 : BUF), cur);
+      if (!more) break;
+      __syncthreads();  // E is read before the buffer is staged again
+      zero_acc();
+      cur = nxt;
+      T = Tn;
+      c = 0;
+    } else {
+      ++c;
+    }
+    buf = other;
   }
 }
 
@@ -797,15 +884,41 @@ hipError_t conv_launch(const ConvArgs &a, int cout_pad, hipStream_t s) {
   return hipGetLastError();
 }
 
-// float32 layers whose inputs come in chunks of 16 channels (all but the
-// first) run as Winograd F(2x2, 3x3); 8 x 32 pixel tiles of 32 output channels
-hipError_t wino_launch(const ConvArgs &a, int cout_pad, bool head, hipStream_t s) {
-  dim3 grid((a.W + 31) / 32, (a.H + 7) / 8, (cout_pad / 32) * a.batch);
+// Float32 layers whose inputs come in chunks of 16 channels (all but the
+// first) run as Winograd F(2x2, 3x3) in persistent workgroups, one resident
+// per CU (LDS), each walking its share of the 8 x 32 pixel tiles.
+template <int MB, int CK>
+hipError_t wino_launch_mc(const ConvArgs &a, int cout_pad, bool head, hipStream_t s) {
+  const int ntx = (a.W + 31) / 32, nty = (a.H + 7) / 8;
+  const int nzc = cout_pad / (32 * MB), ntiles = ntx * nty * nzc * a.batch;
+  static std::atomic<int> cus[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  int n = cus[dev].load(std::memory_order_relaxed);
+  if (n == 0) {
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      return hipErrorInvalidDevice;
+    cus[dev].store(n, std::memory_order_relaxed);
+  }
+  const int grid = ntiles < n ? ntiles : n;
   if (head)
-    wino3x3_kernel<true><<<grid, 512, 0, s>>>(a);
+    wino3x3_kernel<true, MB, CK><<<grid, 512, 0, s>>>(a, ntx, nty, nzc, ntiles);
   else
-    wino3x3_kernel<false><<<grid, 512, 0, s>>>(a);
+    wino3x3_kernel<false, MB, CK><<<grid, 512, 0, s>>>(a, ntx, nty, nzc, ntiles);
   return hipGetLastError();
+}
+// Layers with a multiple of 64 output channels: tiles of 64 channels (each
+// wave reuses its input fragments for two MFMA blocks), staged 8 input
+// channels at a time (two LDS buffers of U for 64 channels must fit), unless
+// one image gives fewer than kSmallGrid such tiles (the 135x240 level of a
+// 1080p frame), where 32-channel tiles keep every CU busy; a layer with the
+// fused head needs all its channels (at most 64) in one tile.  Others: 32
+// channels, 16 input channels at a time.  Both take the same sums in the same
+// order, so the choice does not change results.
+hipError_t wino_launch(const ConvArgs &a, int cout_pad, bool head, hipStream_t s) {
+  const long tiles64 = (long)((a.W + 31) / 32) * ((a.H + 7) / 8) * (cout_pad / 64);
+  if (cout_pad % 64 == 0 && (tiles64 >= kSmallGrid || head)) return wino_launch_mc<2, 8>(a, cout_pad, head, s);
+  return wino_launch_mc<1, 16>(a, cout_pad, head, s);
 }
 
 template <int MODE>
@@ -860,7 +973,7 @@ hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s) {
   while (ck > step && ((c.C0 % ck) != 0 || (c.C1 % ck) != 0)) ck >>= 1;
   if ((c.C0 % ck) != 0 || (c.C1 % ck) != 0 || (c.C0 + c.C1) != L.cin_pad) return hipErrorInvalidValue;
   if (p == Prec::F32 && L.wu && !c.rgbda_depth && c.C0 % 16 == 0 && c.C1 % 16 == 0 &&
-      (!head || L.cout_pad == 32))
+      (!head || L.cout_pad <= 64))
     return wino_launch(a, L.cout_pad, head, s);
   switch (p) {
     case Prec::F32: return conv_dispatch<0>(a, ck, L.cout_pad, s);

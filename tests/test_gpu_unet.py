@@ -59,6 +59,23 @@ def test_unet_random_images(lnr, ctx, prec, widths, H, W, bias):
     assert err <= BOUND[prec], f"prec {prec}: max-abs {err}"
 
 
+def test_unet_fp32_64_channel_tiles(lnr, ctx):
+    """A 64-channel first level on a 392x520 image gives more than 768 tiles
+    of 64 channels, so the float32 layers of that level use 64-channel
+    Winograd tiles, here with a ragged last tile column and the head fused
+    over 64 channels."""
+    H, W = 392, 520
+    blob = synth.make_unet_blob((64, 128), seed=11, bias="uniform")
+    depth, rgba = _random_rgbda(np.random.default_rng(7), H, W)
+    net = U.parse_blob(blob)
+    got = _run(lnr, ctx, lnr.lnr_unet_load(ctx, blob, 0), depth, rgba)
+    # windows the float64 oracle computes on their own: corners (the ragged
+    # last tile column ends at x = 520) and the interior
+    windows = [(0, 40, 0, 40), (H - 40, H, W - 40, W), (176, 216, 250, 290)]
+    err = max(M.max_abs(got[:, a:b, c:d], U.forward_crop(net, depth, rgba, a, b, c, d)) for a, b, c, d in windows)
+    assert err <= BOUND[0], f"max-abs {err}"
+
+
 def test_unet_batchnorm_folding(lnr, ctx):
     blob = synth.make_unet_blob((16, 32), seed=9, bias="uniform", batchnorm=True)
     depth, rgba = _random_rgbda(np.random.default_rng(1), 32, 32)
