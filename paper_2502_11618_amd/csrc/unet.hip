@@ -381,6 +381,20 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     else
       *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
   };
+  // bf16: a lane holds 8 bytes of each of 32 pixels' channel runs, so direct
+  // stores write 16-byte pieces 2 BM bytes apart.  Where LDS allows, each wave
+  // stages its R x 32 pixels x BM channels in LDS ([pixel][channel], 16-byte
+  // pad per pixel) and writes them back as whole 16-byte runs of consecutive
+  // channels, consecutive lanes covering consecutive memory.
+  constexpr int PSTR = BM * 2 + 16;                              // staged bytes per pixel
+  constexpr int STAGE = 4 * R * 32 * PSTR;                       // all waves
+  constexpr bool kStage = MODE == 1 && (STAGE <= (int)sizeof(s_in) || STAGE <= (int)sizeof(s_w));
+  char *stage = nullptr;
+  if constexpr (kStage) {
+    __syncthreads();  // every wave is done with the K loop's LDS
+    char *base = STAGE <= (int)sizeof(s_in) ? reinterpret_cast<char *>(s_in) : reinterpret_cast<char *>(s_w);
+    stage = base + wv * R * 32 * PSTR;
+  }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
@@ -396,8 +410,13 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         for (int i = 0; i < 4; ++i) v[r][i] = fmaxf(acc[mb][r][4 * j + i] + bb[i], 0.f);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int gy = ty0 + row0 + r;
-        if (gy < H && gx < W) put4(out + ((size_t)gy * W + gx) * a.cout + c, v[r]);
+        if constexpr (kStage) {
+          *reinterpret_cast<uint2 *>(stage + (r * 32 + n) * PSTR + (mb * 32 + 8 * j + 4 * h) * 2) =
+              make_uint2(pack_bf16x2(v[r][0], v[r][1]), pack_bf16x2(v[r][2], v[r][3]));
+        } else {
+          const int gy = ty0 + row0 + r;
+          if (gy < H && gx < W) put4(out + ((size_t)gy * W + gx) * a.cout + c, v[r]);
+        }
       }
       if (out_pool) {
 #pragma unroll
@@ -413,6 +432,21 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
             put4(out_pool + ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * a.cout + c, m);
         }
       }
+    }
+  }
+  if constexpr (kStage) {
+    // the wave reads back its own rows (its LDS writes above come first in
+    // order): 16-byte run s of pixel p of row r is item (r 32 + p) BM / 8 + s
+    constexpr int RUNS = BM / 8, ITEMS = R * 32 * RUNS;
+    static_assert(ITEMS % 64 == 0, "whole wave passes");
+#pragma unroll
+    for (int it = 0; it < ITEMS / 64; ++it) {
+      const int item = it * 64 + lane, rp = item / RUNS, run = item - rp * RUNS;
+      const int r = rp >> 5, p = rp & 31;
+      const int gy = ty0 + row0 + r, gxx = tx0 + p, c = co0 + 8 * run;
+      const uint4 x = *reinterpret_cast<const uint4 *>(stage + rp * PSTR + run * 16);
+      if (gy < H && gxx < W && c < a.cout)
+        *reinterpret_cast<uint4 *>(out + ((size_t)gy * W + gxx) * a.cout + c) = x;
     }
   }
 }
