@@ -452,24 +452,25 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 }
 
 // 3x3 convolution in float32 by Winograd's minimal filtering F(2x2, 3x3): each
-// 2x2 block ("tile") of output pixels is Y = A^T [sum_c U_c (.) V_c] A with
-// V_c = B^T d_c B the transform of the tile's 4x4 input patch d_c of channel c
-// and U_c = G g_c G^T the transform of the 3x3 filter (computed on the host);
+// 2x2 block of output pixels is Y = A^T [sum_c U_c (.) V_c] A with
+// V_c = B^T d_c B the transform of the block's 4x4 input patch d_c of channel
+// c and U_c = G g_c G^T the transform of the 3x3 filter (computed on the host);
 //   B^T = [1 0 -1 0; 0 1 1 0; 0 -1 1 0; 0 1 0 -1],
 //   G   = [1 0 0; 1/2 1/2 1/2; 1/2 -1/2 1/2; 0 0 1],
 //   A^T = [1 1 1 0; 0 1 -1 -1].
 // The channel sum is, for each of the 16 transform positions (xi, nu), a GEMM
-// (output channels x tiles, K = input channels) on v_mfma_f32_32x32x2_f32:
-// 16 multiplies per tile and channel pair instead of 36 for the direct form.
-// Workgroup: 8 rows x 32 columns of output pixels (4 x 16 tiles) x 32 output
-// channels, 8 waves; wave w owns transform row xi = w & 3 of tile rows
-// 2 (w >> 2) and 2 (w >> 2) + 1 (32 tiles, one per lane column) and holds the
-// four accumulators (xi, nu = 0..3).  Row xi of B^T d combines two patch rows,
-// so a wave reads 8 of the 16 patch pixels and transforms in registers.
-// The input tile with its halo and the chunk's U (one copy per workgroup) are
-// staged through two LDS buffers, so one barrier per chunk of 16 channels
-// suffices.  Epilogue: each wave reduces its row by A (2 values per tile and
-// channel) into LDS, and every thread then finishes 4 channels of one tile:
+// (output channels x blocks, K = input channels) on v_mfma_f32_32x32x2_f32:
+// 16 multiplies per block and channel pair instead of 36 for the direct form.
+// A tile is 8 rows x 32 columns of output pixels (4 x 16 blocks) x 32 MB output
+// channels.  A workgroup has 8 waves; wave w owns transform row xi = w & 3 of
+// block rows 2 (w >> 2) and 2 (w >> 2) + 1 (32 blocks, one per lane column)
+// and holds the accumulators (xi, nu = 0..3) of MB blocks of 32 channels, so
+// with MB = 2 its input fragments feed two MFMA blocks.  Row xi of B^T d
+// combines two patch rows, so a wave reads 8 of the 16 patch pixels and
+// transforms in registers.  Workgroups are persistent (one per CU) and stream
+// the CK-channel chunks of their tiles through two LDS buffers, one barrier
+// per chunk.  Epilogue: each wave reduces its row by A (2 values per block and
+// channel) into LDS, and every thread then finishes 4 channels of one block:
 // the A^T row reduction, bias, ReLU, the 2x2 output block (which is also the
 // max-pool window) and the fused 1x1 head.
 template <bool HEAD, int MB, int CK>
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a, int ntx, int n
   constexpr int TH = 4 * TB, TW = 32, LW = TW + 2, LPix = (TH + 2) * LW;
   // input tile in LDS, in 16-byte units (4 channels): unit of (row, col, vector v)
   // = v PX + (col & 1) PY + row HZ + (col >> 1).  Lanes read the pixels of 16
-  // consecutive tiles, 2 columns apart: with even and odd columns in separate
+  // consecutive blocks, 2 columns apart: with even and odd columns in separate
   // planes those are 16 consecutive units, one per bank group.
   constexpr int HZ = LW / 2, PY = (TH + 2) * HZ, PX = 2 * PY;
   constexpr int CS = 16 * CK + 4;                    // LDS floats per output channel of U (+4: bank spread)
@@ -588,7 +589,7 @@ __global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a, int ntx, int n
     }
   };
 
-  // lane (n, h): tile (tr, tc) of the workgroup, channels 8g + 4h + s of
+  // lane (n, h): block (tr, tc) of the tile, channels 8g + 4h + s of
   // chunk group g at k-step s.  Row xi of B^T d is patch row ra + sg * patch row rb.
   const int tr = 2 * tb + (n >> 4), tc = n & 15;
   const int ra = xi == 0 ? 0 : (xi == 2 ? 2 : 1);
@@ -597,7 +598,7 @@ __global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a, int ntx, int n
   const int ioa = 4 * (h * PX + (2 * tr + ra) * HZ + tc);
   const int iob = 4 * (h * PX + (2 * tr + rb) * HZ + tc);
   const int iow = INP + n * CS + 4 * xi * CK + 4 * h;
-  // acc[mb][nu]: positions (xi, nu) of output channels co0 + 32 mb + ... of 32 tiles
+  // acc[mb][nu]: positions (xi, nu) of output channels co0 + 32 mb + ... of 32 blocks
   floatx16 acc[MB][4];
   auto zero_acc = [&]() {
 #pragma unroll
@@ -642,8 +643,8 @@ __global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a, int ntx, int n
   // ---- epilogue of one tile into E (EPL floats of LDS nobody reads any
   // more), one block of 32 output channels at a time.  Accumulator register
   // 4j + i of acc[mb][nu] holds position (xi, nu) of channel co0 + 32 mb +
-  // 8j + 4h + i for tile n; each wave reduces nu by A into E, then thread
-  // (tile et, quad q) reduces xi by A^T for channels c .. c + 3.
+  // 8j + 4h + i for block n; each wave reduces nu by A into E, then thread
+  // (block et, quad q) reduces xi by A^T for channels c .. c + 3.
   const int q = tid & 7, et = tid >> 3, etb = et >> 5, en = et & 31;
   auto epilogue = [&](float *E, const TileId &d) {
     const int gy0 = d.ty0 + 2 * (2 * etb + (en >> 4)), gx0 = d.tx0 + 2 * (en & 15);
@@ -734,7 +735,7 @@ __global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a, int ntx, int n
     }
     if constexpr (HEAD) {
       // the tile holds every output channel (cout <= NCO): sum the head over
-      // the tile's 8 threads; thread q < 4 writes pixel (q >> 1, q & 1)
+      // the block's 8 threads; thread q < 4 writes pixel (q >> 1, q & 1)
       float *head_out =
           a.head_outs ? a.head_outs[d.bimg] : (a.head_out ? a.head_out + (size_t)d.bimg * 3 * H * W : nullptr);
 #pragma unroll
