@@ -25,7 +25,7 @@ import dataclasses
 import hashlib
 import os
 from concurrent.futures import ProcessPoolExecutor
-from typing import List, Optional, Tuple
+from typing import Callable, List, Optional, Tuple
 
 import numpy as np
 
@@ -302,7 +302,8 @@ def multiroom_scene(seed: int = 0, n_points: int = 20_000_000, n_scans: int = 4,
                     rooms_x: int = 4, rooms_y: int = 2, room_w: float = 10.0, room_d: float = 15.0,
                     height: float = 6.0, n_boxes: int = 48, n_cyl: int = 24,
                     gap_coverage: float = 0.2, workers: Optional[int] = None,
-                    chunk_rays: int = 1_000_000) -> Scene:
+                    chunk_rays: int = 1_000_000,
+                    progress: Optional[Callable[[str], None]] = None) -> Scene:
     """Multi-room, multi-scan scene.
 
     Default: 40 x 30 x 6 m split into eight 10 x 15 m rooms by interior walls
@@ -393,6 +394,8 @@ def multiroom_scene(seed: int = 0, n_points: int = 20_000_000, n_scans: int = 4,
         x, c = _run_scans(seed * 1000 + k, [scanners[k]], quota[k], prims, [caps[k]], [gains[k]],
                           chunk_rays, workers)
         xs.append(x); cs.append(c)
+        if progress is not None:
+            progress(f"scan {k + 1}/{n_scans}: {x.shape[0]} points")
     return Scene(np.concatenate(xs), np.concatenate(cs), scanners, ((0.0, 0.0, 0.0), (X, Y, Z)),
                  room_centers, scan_rooms, name=f"multiroom-s{seed}-n{n_points}-k{n_scans}")
 
@@ -402,7 +405,8 @@ def _cache_dir() -> str:
 
 
 def scene_for_config(name: str, seed: int = 0, n_points: Optional[int] = None,
-                     cache: bool = True, workers: Optional[int] = None) -> Scene:
+                     cache: bool = True, workers: Optional[int] = None,
+                     progress: Optional[Callable[[str], None]] = None) -> Scene:
     """Named workloads.
 
     room     : 200k-point single-scan room (10 x 8 x 3 m, 20 spheres, 0.5 m cells)
@@ -429,7 +433,7 @@ def scene_for_config(name: str, seed: int = 0, n_points: Optional[int] = None,
     if kind == "room":
         sc = room_scene(seed, params["n_points"], workers=workers)
     else:
-        sc = multiroom_scene(seed, workers=workers, **params)
+        sc = multiroom_scene(seed, workers=workers, progress=progress, **params)
     if cache:
         os.makedirs(_cache_dir(), exist_ok=True)
         tmp = path + f".tmp{os.getpid()}.npz"
