@@ -97,3 +97,24 @@ def test_4k_batch_of_eight_views_equals_alone(lnr, ctx, four_k):
         lnr.lnr_reconstruct(ctx, net, img, alone)
         torch.cuda.synchronize()
         assert np.array_equal(results[i][0], alone.cpu().numpy()), f"view {i} differs from its standalone frame"
+
+
+@pytest.mark.parametrize("frame", [0, 61])
+def test_4k_largest_scene_layout_bit_exact(lnr, ctx, frame):
+    """The largest configuration's building (80 x 60 x 10 m, 32 rooms, 16
+    scans, 2 m cells) at 4M points instead of 300M: projection and the
+    6-level filter of a 4K view of its orbit path, bit for bit."""
+    import torch
+    scene = synth.scene_for_config("huge", seed=0, n_points=4_000_000)
+    cloud = lnr.lnr_cloud_load(ctx, scene.xyz, scene.rgb, 2.0)
+    cam = synth.orbit_path(scene, 120, W, H, FOV)[frame]
+    key, depth, rgba = R.render(G.partition(scene.xyz, scene.rgb, 2.0), cam)
+    fd, fr, _ = F.depth_filter(depth.reshape(H, W), rgba.reshape(H, W, 4), NL, FS)
+    assert (rgba.reshape(H, W, 4)[..., 3] != 0).mean() > 0.02, "the view sees too little of the scene"
+    img = render_gpu(lnr, ctx, cloud, cam)
+    assert_images_equal(image_to_host(img), (key, depth, rgba), f"largest-layout render {frame}")
+    lnr.lnr_depth_filter(ctx, img, NL, FS)
+    torch.cuda.synchronize()
+    _, gd, gr = image_to_host(img)
+    assert_images_equal((None, gd, gr), (None, fd, fr), f"largest-layout filter {frame}")
+    lnr.lnr_cloud_destroy(cloud)
