@@ -635,6 +635,16 @@ def main():
         outs[p] = out.cpu().numpy().astype(np.float64)
     errors = {p: None for p in precs} if args.no_error_check else sampled_error(fd, fr, blob, outs, H, W)
 
+    # z-buffer atomics: the timed frames again, projection only, counting the
+    # atomics each splat issues; and the device's 64-bit atomicMin rate on a
+    # buffer of the image's size (pseudo-random words, then contended words)
+    n_atomics = []
+    for i in range(args.steps):
+        L.lnr_render(ctx, cloud, cams[i % len(cams)], img, L.LNR_RENDER_COUNT_ATOMICS)
+        n_atomics.append(L.lnr_render_atomic_count(ctx))
+    atomic_rate, atomic_ops = L.lnr_measure_atomic_min(ctx, H * W, 0, 1 << 26)
+    atomic_rate_contended, _ = L.lnr_measure_atomic_min(ctx, H * W, 1, 1 << 26)
+
     # rooflines
     p0 = precs[0]
     ks = kernel_stats[p0]
@@ -680,6 +690,13 @@ def main():
                   "frac": round(splat_gbs / PEAK_HBM_GBS, 4), "points_per_launch": n_proc,
                   "avg_launch_ms": round(ks["splat"][0], 4),
                   "points_per_s": round(n_proc / (ks["splat"][0] * 1e-3), 1)},
+        "splat_atomics": {"bound": "atomic", "achieved": round(float(np.mean(n_atomics)) / (ks["splat"][0] * 1e-3), 1),
+                          "peak": round(atomic_rate, 1), "unit": "atomics/s",
+                          "frac": round(float(np.mean(n_atomics)) / (ks["splat"][0] * 1e-3) / atomic_rate, 4),
+                          "atomics_per_frame": round(float(np.mean(n_atomics)), 1),
+                          "peak_kind": f"measured: {atomic_ops} 64-bit atomicMin on pseudo-random words of a "
+                                       f"{W}x{H} buffer",
+                          "contended_peak": round(atomic_rate_contended, 1)},
     }
     for p in precs[1:]:
         kp = kernel_stats[p]

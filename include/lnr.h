@@ -87,6 +87,7 @@ typedef enum { LNR_FP32 = 0, LNR_BF16 = 1, LNR_BF16X3 = 2 } lnr_precision;
 /* lnr_render flag: visit every non-empty cell (no frustum test).  The result
  * is identical; this exists to check that culling is a pure speed-up. */
 #define LNR_RENDER_NO_CULL 1u
+#define LNR_RENDER_COUNT_ATOMICS 2u
 
 /* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the
  * device memory the context, and the clouds and networks loaded through it,
@@ -135,8 +136,10 @@ void lnr_cloud_destroy(lnr_cloud *c);
  * u = a / w, v = b / w (correctly rounded).  A cell is skipped only if no
  * point in it can pass the per-point test (float64 bound with slack), so
  * culling never changes the image.  out->key, depth and rgba must all be
- * non-NULL with out->width/height equal to the camera's.  flags: 0 or
- * LNR_RENDER_NO_CULL. */
+ * non-NULL with out->width/height equal to the camera's.  flags: 0 or any of
+ * LNR_RENDER_NO_CULL, LNR_RENDER_COUNT_ATOMICS (also count the z-buffer
+ * atomicMin operations the projection issues, for lnr_render_atomic_count;
+ * the image is the same, the projection somewhat slower: for measurement). */
 lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out, uint32_t flags,
                       void *hip_stream);
 /* Render with the soft z-buffer of Method, "Point Cloud Projection" (colours of
@@ -155,6 +158,26 @@ lnr_status lnr_render_soft(lnr_context *ctx, const lnr_cloud *c, const lnr_camer
  * of the cloud last rendered, 1 = visible. */
 lnr_status lnr_render_stats(lnr_context *ctx, uint64_t *visible_cells, uint64_t *processed_points,
                             uint8_t *cull_flags_host);
+/* Number of z-buffer atomicMin operations issued by the last render on ctx,
+ * which must have been issued with LNR_RENDER_COUNT_ATOMICS (else
+ * LNR_E_INVALID_ARG); waits for ctx's last stream.  A point issues one when
+ * its key is below the pixel's key as last read (Method, "Point Cloud
+ * Projection": the z-buffer keeps the nearest point). */
+lnr_status lnr_render_atomic_count(lnr_context *ctx, uint64_t *atomics);
+/* Roofline denominator of the projection step: the device's throughput of
+ * 64-bit atomicMin, the z-buffer's operation.  Allocates n_slots u64 words
+ * (charged to the context's budget; freed before returning), sets them to
+ * all ones, runs one untimed pass and one timed pass of n_ops operations
+ * (rounded up to a multiple of 16384; *ops_done, if not NULL, receives the
+ * count) on hip_stream, and waits for it.  pattern 0: every operation hits a
+ * pseudo-random word (many points spread over an image); pattern 1: the 64
+ * lanes of a wave hit one word (contention).  *ops_per_s = operations / time
+ * between HIP events around the timed pass.  Errors: LNR_E_INVALID_ARG for
+ * n_slots outside [1, 2^32), pattern not 0 or 1, n_ops outside
+ * [1, 16384 (2^31 - 1)] or NULL ops_per_s; allocation and device errors as
+ * elsewhere. */
+lnr_status lnr_measure_atomic_min(lnr_context *ctx, uint64_t n_slots, int32_t pattern, uint64_t n_ops,
+                                  void *hip_stream, double *ops_per_s, uint64_t *ops_done);
 
 /* Depth filter, in place (Method, "Depth filtering" and Fig. 2): min-pool the
  * depth n_levels times (2x2, stride 2, empty = +inf), then upsample level by

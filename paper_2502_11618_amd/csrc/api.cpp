@@ -42,6 +42,7 @@ struct lnr_context {
   std::string err;
   hipStream_t last_stream = nullptr;
   bool rendered = false;
+  bool counted = false;  // the last render counted its z-buffer atomics
   uint32_t last_cells = 0;
   Scratch sc;
   // kernel timing
@@ -642,7 +643,8 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   if (soft && !(std::isfinite(soft_eps) && soft_eps >= 0.f))
     return fail(ctx, LNR_E_INVALID_ARG, "soft_eps must be finite and >= 0");
   if (!c || !cam || !out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
-  if (flags & ~LNR_RENDER_NO_CULL) return fail(ctx, LNR_E_INVALID_ARG, "unknown render flags");
+  if (flags & ~(LNR_RENDER_NO_CULL | LNR_RENDER_COUNT_ATOMICS))
+    return fail(ctx, LNR_E_INVALID_ARG, "unknown render flags");
   std::string why;
   if (!camera_ok(cam, &why)) return fail(ctx, LNR_E_INVALID_ARG, why);
   if (!out->key || !out->depth || !out->rgba) return fail(ctx, LNR_E_INVALID_ARG, "image buffers must be non-NULL");
@@ -671,7 +673,9 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   LNR_LAUNCH(ctx, "clear", s, launch_clear(out->key, npix, counters, s));
   LNR_LAUNCH(ctx, "cull", s, launch_cull(c->d, prm, static_cast<uint8_t *>(scr.flags.p), static_cast<uint2 *>(scr.chunks.p),
                            counters, s));
-  LNR_LAUNCH(ctx, "splat", s, launch_splat(c->d, static_cast<const uint2 *>(scr.chunks.p), counters, sc, out->key, s));
+  const bool count = (flags & LNR_RENDER_COUNT_ATOMICS) != 0;
+  LNR_LAUNCH(ctx, "splat", s,
+             launch_splat(c->d, static_cast<const uint2 *>(scr.chunks.p), counters, sc, out->key, count, s));
   if (soft) {
     if ((st = ensure(ctx, scr.soft_acc, 16ull * npix)) != LNR_OK) return st;
     LNR_LAUNCH(ctx, "soft", s,
@@ -684,6 +688,7 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   }
   ctx->last_stream = s;
   ctx->rendered = true;
+  ctx->counted = count;
   ctx->last_cells = c->d.n_cells;
   return LNR_OK;
 }
@@ -711,6 +716,56 @@ lnr_status lnr_render_stats(lnr_context *ctx, uint64_t *visible_cells, uint64_t 
   if (processed_points) *processed_points = (uint64_t)cnt[2] | ((uint64_t)cnt[3] << 32);
   if (cull_flags_host)
     LNR_HIP(ctx, hipMemcpy(cull_flags_host, ctx->sc.flags.p, ctx->last_cells, hipMemcpyDeviceToHost));
+  return LNR_OK;
+}
+
+lnr_status lnr_render_atomic_count(lnr_context *ctx, uint64_t *atomics) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!atomics) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
+  if (!ctx->rendered || !ctx->counted)
+    return fail(ctx, LNR_E_INVALID_ARG, "the last render on this context did not count its atomics");
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  LNR_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
+  uint32_t cnt[kCounterWords];
+  LNR_HIP(ctx, hipMemcpy(cnt, ctx->sc.counters.p, sizeof(cnt), hipMemcpyDeviceToHost));
+  *atomics = cnt[kAtomicWord];
+  return LNR_OK;
+}
+
+lnr_status lnr_measure_atomic_min(lnr_context *ctx, uint64_t n_slots, int32_t pattern, uint64_t n_ops,
+                                  void *hip_stream, double *ops_per_s, uint64_t *ops_done) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!ops_per_s) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
+  if (n_slots < 1 || n_slots > 0xffffffffull) return fail(ctx, LNR_E_INVALID_ARG, "n_slots must be in [1, 2^32)");
+  if (pattern != 0 && pattern != 1) return fail(ctx, LNR_E_INVALID_ARG, "pattern must be 0 or 1");
+  constexpr uint64_t per_block = 256ull * kProbeIters;
+  if (n_ops < 1 || n_ops > per_block * 0x7fffffffull) return fail(ctx, LNR_E_INVALID_ARG, "n_ops out of range");
+  lnr_status st = use_device(ctx);
+  if (st != LNR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const uint32_t grid = (uint32_t)((n_ops + per_block - 1) / per_block);
+  TempAllocs tmp(ctx);
+  uint64_t *buf;
+  if ((st = tmp.get(&buf, 8ull * n_slots)) != LNR_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  LNR_HIP(ctx, hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  float ms = 0.f;
+  if (he == hipSuccess) he = hipMemsetAsync(buf, 0xff, 8ull * n_slots, s);
+  if (he == hipSuccess) he = launch_atomic_probe(buf, (uint32_t)n_slots, pattern, grid, 1u, s);  // warm-up
+  if (he == hipSuccess) he = hipMemsetAsync(buf, 0xff, 8ull * n_slots, s);
+  if (he == hipSuccess) he = hipEventRecord(e0, s);
+  if (he == hipSuccess) he = launch_atomic_probe(buf, (uint32_t)n_slots, pattern, grid, 2u, s);
+  if (he == hipSuccess) he = hipEventRecord(e1, s);
+  if (he == hipSuccess) he = hipEventSynchronize(e1);
+  if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  LNR_HIP(ctx, he);
+  const uint64_t done = (uint64_t)grid * per_block;
+  *ops_per_s = ms > 0.f ? (double)done / (ms * 1e-3) : 0.0;
+  if (ops_done) *ops_done = done;
   return LNR_OK;
 }
 

@@ -58,8 +58,10 @@ struct SplatCam {
 };
 
 // counters written by the render kernels: [0] chunks, [1] visible cells,
-// [2..3] processed points (u64), [4 + b] chunks queued in depth bucket b
-constexpr int kCounterWords = 4 + kDepthBuckets;
+// [2..3] processed points (u64), [4 + b] chunks queued in depth bucket b,
+// [kAtomicWord] z-buffer atomics issued (counting renders only)
+constexpr int kAtomicWord = 4 + kDepthBuckets;
+constexpr int kCounterWords = kAtomicWord + 1;
 
 // ----------------------------------------------------------------------------
 // kernel launchers (each returns hipGetLastError() of its launches)
@@ -89,8 +91,15 @@ hipError_t launch_chunk_count(const uint32_t *cell_start, uint32_t n_cells, uint
 hipError_t launch_clear(uint64_t *key, uint32_t npix, uint32_t *counters, hipStream_t s);
 hipError_t launch_cull(const CloudDev &c, const CullParams &prm, uint8_t *flags, uint2 *chunks, uint32_t *counters,
                        hipStream_t s);
-hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, const uint32_t *counters, const SplatCam &cam,
-                        uint64_t *key, hipStream_t s);
+// count_atomics: also add the number of z-buffer atomics issued to counters[kAtomicWord]
+hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counters, const SplatCam &cam,
+                        uint64_t *key, bool count_atomics, hipStream_t s);
+// throughput probe: grid x 256 threads x iters 64-bit atomicMin on buf[n_slots]
+// (pattern 0: pseudo-random words; 1: one word per wave, consecutive waves
+// consecutive words)
+constexpr uint32_t kProbeIters = 64;
+hipError_t launch_atomic_probe(uint64_t *buf, uint32_t n_slots, int pattern, uint32_t grid, uint32_t seed,
+                               hipStream_t s);
 hipError_t launch_resolve(const uint64_t *key, const uint32_t *rgbx, float *depth, uint32_t *rgba, uint32_t npix,
                           hipStream_t s);
 // soft z-buffer: clear the colour sums, accumulate, resolve (acc = 4 x u32 per pixel)

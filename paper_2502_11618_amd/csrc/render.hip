@@ -125,13 +125,17 @@ __device__ inline bool work_item(uint32_t i, const uint32_t *__restrict__ counte
 
 // One block per work item.  Keys only ever decrease, so a plain (possibly
 // stale) read of the pixel's key is an upper bound of its current value and
-// the atomic can be skipped when the new key is not smaller.
+// the atomic can be skipped when the new key is not smaller.  COUNT adds the
+// number of atomics issued to counters[kAtomicWord] (one add per wave), for
+// measurement; the keys written are the same.
+template <bool COUNT>
 __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
                                                          const float *__restrict__ zs, const uint2 *__restrict__ chunks,
-                                                         uint32_t cap, const uint32_t *__restrict__ counters,
+                                                         uint32_t cap, uint32_t *__restrict__ counters,
                                                          SplatCam cam, uint64_t *__restrict__ key) {
   uint2 ch;
   if (!work_item(blockIdx.x, counters, chunks, cap, &ch)) return;
+  uint32_t issued = 0;
   const float *P = cam.P;
   // (keeping several points per thread in flight was measured slower: the
   // kernel is bound by the z-buffer atomics, not by load latency)
@@ -147,7 +151,41 @@ __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict
     if (!(u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf)) continue;
     const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | j;
     uint64_t *dst = key + (size_t)(uint32_t)v * cam.W + (uint32_t)u;
-    if (k < *dst) atomicMin(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)k);
+    if (k < *dst) {
+      atomicMin(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)k);
+      if constexpr (COUNT) ++issued;
+    }
+  }
+  if constexpr (COUNT) {
+    for (int off = 32; off > 0; off >>= 1) issued += __shfl_xor(issued, off, 64);
+    if ((threadIdx.x & 63) == 0 && issued) atomicAdd(&counters[kAtomicWord], issued);
+  }
+}
+
+// Throughput probe for the z-buffer's operation: each thread issues
+// kProbeIters 64-bit atomicMin.  Pattern 0 draws the word of each from a
+// per-thread xorshift32 sequence (Marsaglia's 13/17/5 shifts), so the
+// operations spread over the buffer as a splat's do over the image; pattern 1
+// sends the 64 lanes of a wave to one word.  Values decrease along each
+// thread's sequence, so most operations lower the word.
+__global__ __launch_bounds__(kThreads) void atomic_probe_kernel(uint64_t *__restrict__ buf, uint32_t n_slots,
+                                                                int pattern, uint32_t seed) {
+  const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
+  uint32_t x = (gid + 1u) * 0x9E3779B9u ^ seed;
+  if (x == 0) x = 1u;
+  const uint32_t wave = gid >> 6, nwaves = gridDim.x * (kThreads / 64);
+  for (uint32_t i = 0; i < kProbeIters; ++i) {
+    uint32_t slot;
+    if (pattern == 0) {
+      x ^= x << 13;
+      x ^= x >> 17;
+      x ^= x << 5;
+      slot = x % n_slots;
+    } else {
+      slot = (i * nwaves + wave) % n_slots;
+    }
+    const uint64_t v = ((uint64_t)(kProbeIters - i) << 32) | gid;
+    atomicMin(reinterpret_cast<unsigned long long *>(buf + slot), (unsigned long long)v);
   }
 }
 
@@ -248,10 +286,20 @@ hipError_t launch_cull(const CloudDev &c, const CullParams &prm, uint8_t *flags,
   return hipGetLastError();
 }
 
-hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, const uint32_t *counters, const SplatCam &cam,
-                        uint64_t *key, hipStream_t s) {
+hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counters, const SplatCam &cam,
+                        uint64_t *key, bool count_atomics, hipStream_t s) {
   if (c.max_chunks == 0) return hipSuccess;
-  splat_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, c.max_chunks, counters, cam, key);
+  if (count_atomics)
+    splat_kernel<true><<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, c.max_chunks, counters, cam, key);
+  else
+    splat_kernel<false><<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, c.max_chunks, counters, cam, key);
+  return hipGetLastError();
+}
+
+hipError_t launch_atomic_probe(uint64_t *buf, uint32_t n_slots, int pattern, uint32_t grid, uint32_t seed,
+                               hipStream_t s) {
+  if (n_slots == 0 || grid == 0) return hipErrorInvalidValue;
+  atomic_probe_kernel<<<grid, kThreads, 0, s>>>(buf, n_slots, pattern, seed);
   return hipGetLastError();
 }
 

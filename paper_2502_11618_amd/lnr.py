@@ -30,6 +30,7 @@ LNR_BF16 = 1
 LNR_BF16X3 = 2
 
 LNR_RENDER_NO_CULL = 1
+LNR_RENDER_COUNT_ATOMICS = 2
 
 EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
 
@@ -107,6 +108,9 @@ def _load():
         "lnr_render_soft": (i32, [vp, vp, ctypes.POINTER(lnr_camera), ctypes.POINTER(lnr_image), f32, ctypes.c_uint32,
                                   vp]),
         "lnr_render_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), vp]),
+        "lnr_render_atomic_count": (i32, [vp, ctypes.POINTER(u64)]),
+        "lnr_measure_atomic_min": (i32, [vp, u64, i32, u64, vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(u64)]),
         "lnr_depth_filter": (i32, [vp, ctypes.POINTER(lnr_image), i32, f32, vp]),
         "lnr_unet_load": (i32, [vp, vp, u64, ctypes.c_int, ctypes.POINTER(vp)]),
         "lnr_unet_destroy": (None, [vp]),
@@ -313,6 +317,21 @@ def lnr_render_stats(ctx: Context, n_cells: Optional[int] = None):
     _check(_lib.lnr_render_stats(ctx.handle, ctypes.byref(vis), ctypes.byref(proc),
                                  flags.ctypes.data if flags is not None else None), ctx.handle)
     return vis.value, proc.value, flags
+
+
+def lnr_render_atomic_count(ctx: Context) -> int:
+    n = ctypes.c_uint64()
+    _check(_lib.lnr_render_atomic_count(ctx.handle, ctypes.byref(n)), ctx.handle)
+    return n.value
+
+
+def lnr_measure_atomic_min(ctx: Context, n_slots: int, pattern: int, n_ops: int, stream=None):
+    """(operations per second, operations timed)"""
+    rate = ctypes.c_double()
+    done = ctypes.c_uint64()
+    _check(_lib.lnr_measure_atomic_min(ctx.handle, int(n_slots), int(pattern), int(n_ops), _stream(stream),
+                                       ctypes.byref(rate), ctypes.byref(done)), ctx.handle)
+    return rate.value, done.value
 
 
 def lnr_depth_filter(ctx: Context, image: Image, n_levels: int, filter_strength: float, stream=None) -> None:

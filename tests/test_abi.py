@@ -58,3 +58,12 @@ def test_binding_has_every_declared_entry_point():
     import paper_2502_11618_amd.lnr as B
     missing = [n for n in _declared() if not callable(getattr(B, n, None))]
     assert not missing, missing
+
+
+def test_atomic_entry_points_reject_bad_arguments_without_a_device():
+    import paper_2502_11618_amd as L
+    lib = L.lib
+    rate = ctypes.c_double()
+    n = ctypes.c_uint64()
+    assert lib.lnr_render_atomic_count(None, ctypes.byref(n)) == L.LNR_E_INVALID_ARG
+    assert lib.lnr_measure_atomic_min(None, 16, 0, 1024, None, ctypes.byref(rate), None) == L.LNR_E_INVALID_ARG

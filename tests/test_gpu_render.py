@@ -183,3 +183,46 @@ def test_objects_outlive_a_destroyed_context(lnr, ctx, room_scene, room_grid, ro
     lnr.lnr_cloud_destroy(cloud)    # frees the context too
     fresh = lnr.lnr_cloud_load(ctx, room_scene.xyz, room_scene.rgb, 0.5)
     assert_images_equal(image_to_host(render_gpu(lnr, ctx, fresh, cam)), R.render(room_grid, cam), "fresh cloud")
+
+
+@pytest.mark.parametrize("i", [0, 5, 11])
+def test_counting_render_is_bit_exact_and_counts_plausibly(lnr, ctx, room_cloud, room_grid, room_cams, i):
+    """The atomic-counting projection writes the same image; its count of
+    z-buffer atomics lies between the filled pixels (the first point on an
+    empty pixel always issues one) and the processed points (at most one per
+    point).  The count depends on the order points arrive in, so only these
+    bounds are checked."""
+    cam = room_cams[i]
+    plain = image_to_host(render_gpu(lnr, ctx, room_cloud, cam))
+    img = render_gpu(lnr, ctx, room_cloud, cam, flags=lnr.LNR_RENDER_COUNT_ATOMICS)
+    counted = image_to_host(img)
+    assert_images_equal(counted, plain, f"counting render {i}")
+    assert_images_equal(counted, R.render(room_grid, cam), f"counting render {i} vs oracle")
+    n = lnr.lnr_render_atomic_count(ctx)
+    _, processed, _ = lnr.lnr_render_stats(ctx)
+    filled = int((counted[2].reshape(-1, 4)[:, 3] != 0).sum())
+    assert filled > 0
+    assert filled <= n <= processed
+    render_gpu(lnr, ctx, room_cloud, cam)
+    with pytest.raises(lnr.LnrError) as e:
+        lnr.lnr_render_atomic_count(ctx)
+    assert e.value.status == lnr.LNR_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("pattern", [0, 1])
+def test_atomic_min_probe(lnr, ctx, pattern):
+    """The throughput probe runs whole blocks of 256 x 64 operations and
+    returns a positive rate; it frees its buffer and rejects bad arguments."""
+    before = lnr.lnr_allocated_bytes(ctx)
+    rate, done = lnr.lnr_measure_atomic_min(ctx, 1920 * 1080, pattern, 1 << 22)
+    assert done == 1 << 22
+    assert 1e8 < rate < 1e14
+    rate2, done2 = lnr.lnr_measure_atomic_min(ctx, 7, pattern, 1)
+    assert done2 == 256 * 64 and rate2 > 0
+    assert lnr.lnr_allocated_bytes(ctx) == before
+    for bad in [dict(n_slots=0), dict(n_slots=1 << 32), dict(pattern=2), dict(n_ops=0)]:
+        kw = dict(n_slots=1024, pattern=pattern, n_ops=1024)
+        kw.update(bad)
+        with pytest.raises(lnr.LnrError) as e:
+            lnr.lnr_measure_atomic_min(ctx, **kw)
+        assert e.value.status == lnr.LNR_E_INVALID_ARG
