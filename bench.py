@@ -507,6 +507,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="fp32,bf16x3,bf16")
     ap.add_argument("--no-error-check", action="store_true", help="skip the float64 error windows")
+    ap.add_argument("--pipelined", action="store_true",
+                    help="overlap the next frame's projection and filter (second stream and context) with the "
+                         "current frame's U-Net (default: frames one after the other on one stream)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="serving run length (0 = skip)")
     ap.add_argument("--mode", default="frames", choices=["frames", "copy", "counters", "precision-tier", "largest"],
                     help="copy: only a plain 1 GiB device copy (calibrates HBM byte counters); "
@@ -574,21 +577,56 @@ def main():
         L.lnr_depth_filter(ctx, img, NL, FS)
         L.lnr_reconstruct(ctx, net, img, out)
 
+    # Pipelined frames: frame i's projection and filter run on their own
+    # stream (and context: a context's calls must not overlap on two streams)
+    # while frame i - 1's U-Net runs on the U-Net stream; two RGBDA images
+    # alternate, an image being re-rendered only after the U-Net that read it.
+    if args.pipelined:
+        ctx_geo = L.lnr_context_create(0)
+        s_geo, s_net = torch.cuda.Stream(), torch.cuda.current_stream()
+        imgs = [L.Image(H, W), L.Image(H, W)]
+        ready = [torch.cuda.Event(), torch.cuda.Event()]
+        done = [torch.cuda.Event(), torch.cuda.Event()]
+        for e in done:
+            e.record(s_net)
+
+    def frame_pipelined(i, net, ev=None):
+        g = i & 1
+        s_geo.wait_event(done[g])
+        if ev is not None:
+            ev[0].record(s_geo)
+        L.lnr_render(ctx_geo, cloud, cams[i % len(cams)], imgs[g], stream=s_geo)
+        L.lnr_depth_filter(ctx_geo, imgs[g], NL, FS, stream=s_geo)
+        ready[g].record(s_geo)
+        s_net.wait_event(ready[g])
+        L.lnr_reconstruct(ctx, net, imgs[g], out, stream=s_net)
+        done[g].record(s_net)
+        if ev is not None:
+            ev[1].record(s_net)
+
+    run_frame = frame_pipelined if args.pipelined else frame
+
     results = {}
     kernel_stats = {}
     for p in precs:
         net = nets[p]
         for i in range(args.warmup):
-            frame(i, net)
+            run_frame(i, net)
+            if args.pipelined:
+                frame(i, net)  # the per-kernel pass below runs sequential frames
         torch.cuda.synchronize()
-        # pass 1: frame rate and per-frame latency (one event pair per frame)
+        # pass 1: frame rate and per-frame latency (one event pair per frame,
+        # from the start of its projection to the end of its U-Net)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
-            ev[i][0].record()
-            frame(i, net)
-            ev[i][1].record()
+            if args.pipelined:
+                frame_pipelined(i, net, ev[i])
+            else:
+                ev[i][0].record()
+                frame(i, net)
+                ev[i][1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         lat = np.array([a.elapsed_time(b) for a, b in ev])
@@ -723,7 +761,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "multiroom-20M-pts-1920x1080-orbit120", "points": scene.n, "scans": 4,
                    "cell_m": 1.0, "width": W, "height": H, "fov_deg": FOV, "n_levels": NL, "filter_strength": FS,
-                   "unet_widths": list(widths), "frames": len(cams), "grid_dims": list(info["dims"])},
+                   "unet_widths": list(widths), "frames": len(cams), "grid_dims": list(info["dims"]),
+                   "pipelined": bool(args.pipelined)},
         "latency_ms": {k: round(v, 4) for k, v in results[p0]["latency_ms"].items()},
         "points_per_s": round(n_proc * fps, 1),
         "processed_points_per_frame": round(n_proc, 1),

@@ -135,3 +135,45 @@ def test_soft_zbuffer_sessions_equal_alone(lnr, ctx, room_scene, room_cloud):
             lnr.lnr_reconstruct(ctx, net, img, out)
             torch.cuda.synchronize()
             assert np.array_equal(res[f * 100 + i][0], out.cpu().numpy()), f"session {i} frame {f}"
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_context_frame_pipeline_equals_sequential(lnr, ctx, room_cloud, room_cams, prec):
+    """The frame pipeline the bench times: projection and filter of frame i on
+    one stream and context while the U-Net of frame i - 1 runs on another,
+    two RGBDA images alternating.  Every frame's output equals the frame
+    computed alone on one stream, bit for bit."""
+    import torch
+    W = H = 256
+    net = lnr.lnr_unet_load(ctx, synth.make_unet_blob((16, 32, 64), seed=3), prec)
+    ctx_geo = lnr.lnr_context_create(0)
+    alone = []
+    img = lnr.Image(H, W)
+    for cam in room_cams[:6]:
+        lnr.lnr_render(ctx, room_cloud, cam, img)
+        lnr.lnr_depth_filter(ctx, img, 4, 0.5)
+        o = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
+        lnr.lnr_reconstruct(ctx, net, img, o)
+        alone.append(o)
+    torch.cuda.synchronize()
+    s_geo, s_net = torch.cuda.Stream(), torch.cuda.current_stream()
+    imgs = [lnr.Image(H, W), lnr.Image(H, W)]
+    ready = [torch.cuda.Event(), torch.cuda.Event()]
+    done = [torch.cuda.Event(), torch.cuda.Event()]
+    for e in done:
+        e.record(s_net)
+    outs = []
+    for i, cam in enumerate(room_cams[:6]):
+        g = i & 1
+        s_geo.wait_event(done[g])
+        lnr.lnr_render(ctx_geo, room_cloud, cam, imgs[g], stream=s_geo)
+        lnr.lnr_depth_filter(ctx_geo, imgs[g], 4, 0.5, stream=s_geo)
+        ready[g].record(s_geo)
+        s_net.wait_event(ready[g])
+        o = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
+        lnr.lnr_reconstruct(ctx, net, imgs[g], o, stream=s_net)
+        done[g].record(s_net)
+        outs.append(o)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(alone, outs)):
+        assert torch.equal(a, b), f"frame {i} differs in the pipeline"
