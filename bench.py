@@ -690,8 +690,9 @@ def main():
     shapes = conv_shapes(widths, H, W, cin0)
     flops = {name: 2.0 * h * w * co * 9 * ci for (name, h, w, co, ci) in shapes}
     # float32 layers past the first run as Winograd F(2x2, 3x3): 16 multiplies
-    # per 2x2 output block and channel pair on the matrix cores (direct: 36)
-    mfma_flops = {name: (2.0 * ((h + 1) // 2) * ((w + 1) // 2) * 16 * co * ci if i > 0 else flops[name])
+    # per 2x2 output block and channel pair on the matrix cores (direct: 36);
+    # the first layer multiplies 6 of its 8 staged channels (3 k-pairs) per tap
+    mfma_flops = {name: (2.0 * ((h + 1) // 2) * ((w + 1) // 2) * 16 * co * ci if i > 0 else 2.0 * h * w * co * 9 * 6)
                   for i, (name, h, w, co, ci) in enumerate(shapes)}
     conv_ms = {k: v[0] for k, v in ks.items() if k.startswith("conv/")}
     dom = max(conv_ms, key=conv_ms.get)

@@ -952,10 +952,13 @@ lnr_status lnr_unet_load(lnr_context *ctx, const void *blob_host, uint64_t bytes
     cl.cin_pad = (li == 0) ? u->cin0_pad : (int)ci;
     const size_t np = (size_t)cl.cout_pad * 9 * cl.cin_pad;
     std::vector<float> packed(np, 0.f);
+    // the float32 network input is staged as (x0, x1, x2, 0, x3, x4, 0, 0)
+    const bool gap = li == 0 && u->prec == Prec::F32;
     for (int o = 0; o < (int)co; ++o)
       for (int i = 0; i < (int)ci; ++i)
         for (int t = 0; t < 9; ++t)
-          packed[((size_t)o * 9 + t) * cl.cin_pad + i] = (float)Wd[((size_t)o * ci + i) * 9 + t];
+          packed[((size_t)o * 9 + t) * cl.cin_pad + (gap && i >= 3 ? i + 1 : i)] =
+              (float)Wd[((size_t)o * ci + i) * 9 + t];
     std::vector<float> bias(cl.cout_pad, 0.f);
     for (int o = 0; o < (int)co; ++o) bias[o] = (float)bd[o];
     void *bp;

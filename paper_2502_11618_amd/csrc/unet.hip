@@ -183,6 +183,11 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if constexpr (MODE == 1) {
           if (qi == 0) v = make_uint4(pack_bf16x2(x0, x1), pack_bf16x2(x2, x3), pack_bf16x2(x4, 0.f), 0u);
+        } else if constexpr (MODE == 0) {
+          // channels (x0, x1, x2, 0 | x3, x4, 0, 0): k-steps pair channel s
+          // with channel 4 + s, so the fourth pair is zero and skipped
+          if (qi == 0) v = make_uint4(__float_as_uint(x0), __float_as_uint(x1), __float_as_uint(x2), 0u);
+          if (qi == 4) v = make_uint4(__float_as_uint(x3), __float_as_uint(x4), 0u, 0u);
         } else {
           if (qi == 0) v = make_uint4(__float_as_uint(x0), __float_as_uint(x1), __float_as_uint(x2), __float_as_uint(x3));
           if (qi == 4) v = make_uint4(__float_as_uint(x4), 0u, 0u, 0u);
@@ -274,7 +279,9 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
             acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.x, bv4.x, acc[mb][r], 0, 0, 0);
             acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.y, bv4.y, acc[mb][r], 0, 0, 0);
             acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.z, bv4.z, acc[mb][r], 0, 0, 0);
-            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.w, bv4.w, acc[mb][r], 0, 0, 0);
+            // the staged network input has zeros in channels 3 and 7
+            if constexpr (!RGBDA)
+              acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av4.w, bv4.w, acc[mb][r], 0, 0, 0);
           } else if constexpr (MODE == 1) {
             acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(f.a[0][mb][dy]), as_bf16x8(f.b[0][r + dy]),
                                                                  acc[mb][r], 0, 0, 0);
@@ -833,7 +840,9 @@ __global__ __launch_bounds__(512) void wino3x3_kernel(ConvArgs a, int ntx, int n
 }
 
 // RGBDA -> network input x = (r/255, g/255, b/255, A ? D/16 : 0, A, 0...), cpad channels
-template <int MODE>
+// GAP: the float32 network's channel order (x0, x1, x2, 0, x3, x4, 0, 0), the
+// one its first convolution stages; otherwise (x0, ..., x4, 0, ...)
+template <int MODE, bool GAP>
 __global__ __launch_bounds__(256) void pack_kernel(const float *__restrict__ depth, const uint32_t *__restrict__ rgba,
                                                    int npix, int cpad, void *__restrict__ x) {
   const int p = blockIdx.x * 256 + threadIdx.x;
@@ -846,8 +855,8 @@ __global__ __launch_bounds__(256) void pack_kernel(const float *__restrict__ dep
   v[0] = (float)(q & 255u) / 255.0f;
   v[1] = (float)((q >> 8) & 255u) / 255.0f;
   v[2] = (float)((q >> 16) & 255u) / 255.0f;
-  v[3] = A ? depth[p] * 0.0625f : 0.f;
-  v[4] = A ? 1.f : 0.f;
+  v[GAP ? 4 : 3] = A ? depth[p] * 0.0625f : 0.f;
+  v[GAP ? 5 : 4] = A ? 1.f : 0.f;
   if (MODE == 1) {  // cpad is 16: two 16-byte stores
     uint4 *o = reinterpret_cast<uint4 *>(static_cast<uint16_t *>(x) + (size_t)p * cpad);
     o[0] = make_uint4(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]), pack_bf16x2(v[4], v[5]), pack_bf16x2(v[6], v[7]));
@@ -989,9 +998,11 @@ hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, in
   const int npix = H * W;
   const int nb = (npix + 255) / 256;
   if (p == Prec::BF16)
-    pack_kernel<1><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
+    pack_kernel<1, false><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
+  else if (p == Prec::F32)
+    pack_kernel<0, true><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
   else
-    pack_kernel<0><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
+    pack_kernel<0, false><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
   return hipGetLastError();
 }
 
