@@ -983,7 +983,8 @@ hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s)
       return ck == 32 ? conv_launch<1, 32, 32, 2>(a, cout_pad, s) : conv_launch<1, 32, 16, 2>(a, cout_pad, s);
     if (a.C0 + a.C1 > 32)
       return ck == 32 ? conv_launch<1, 32, 32, 4>(a, cout_pad, s) : conv_launch<1, 32, 16, 4>(a, cout_pad, s);
-    return ck == 32 ? conv_launch<1, 32, 32, 2>(a, cout_pad, s) : conv_launch<1, 32, 16, 2>(a, cout_pad, s);
+    // the layer with the fused head: 16-channel chunks measured faster (the same sums in the same order)
+    return ck == 32 && !head ? conv_launch<1, 32, 32, 2>(a, cout_pad, s) : conv_launch<1, 32, 16, 2>(a, cout_pad, s);
   } else {
     if (ck < 16) return hipErrorInvalidValue;
     if (wide) return conv_launch<2, 64, 16, 2>(a, cout_pad, s);
