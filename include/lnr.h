@@ -75,14 +75,21 @@ typedef struct {
   int32_t width, height;
 } lnr_image;
 
-/* U-Net arithmetic.
- *   LNR_FP32   : float32 activations, float32 matrix-core products.
- *   LNR_BF16   : bfloat16 activations and weights, float32 accumulation.
- *   LNR_BF16X3 : float32 activations; each operand split into bfloat16
- *                high + low parts and multiplied as hi*hi + hi*lo + lo*hi
- *                with float32 accumulation (near-float32 accuracy on
- *                bfloat16 matrix cores). */
-typedef enum { LNR_FP32 = 0, LNR_BF16 = 1, LNR_BF16X3 = 2 } lnr_precision;
+/* U-Net arithmetic (the paper fixes none; Method, "U-Net Reconstruction").
+ *   LNR_FP32     : float32 activations, float32 matrix-core products.
+ *   LNR_BF16     : bfloat16 activations and weights, float32 accumulation.
+ *   LNR_FP8_E4M3 : OCP e4m3 operands with per-output-channel weight scales,
+ *                  float32 accumulation.  This build returns
+ *                  LNR_E_UNSUPPORTED for it from lnr_unet_load.
+ *   LNR_BF16X3   : float32 activations; each operand split into bfloat16
+ *                  high + low parts and multiplied as hi*hi + hi*lo + lo*hi
+ *                  with float32 accumulation (near-float32 accuracy on
+ *                  bfloat16 matrix cores).
+ *   LNR_FP16     : IEEE binary16 activations and weights, float32
+ *                  accumulation: the data movement and matrix rate of
+ *                  LNR_BF16 with a 10- instead of a 7-bit fraction.
+ * Every precision computes the same network; only the rounding differs. */
+typedef enum { LNR_FP32 = 0, LNR_BF16 = 1, LNR_FP8_E4M3 = 2, LNR_BF16X3 = 3, LNR_FP16 = 4 } lnr_precision;
 
 /* lnr_render flag: visit every non-empty cell (no frustum test).  The result
  * is identical; this exists to check that culling is a pure speed-up. */
@@ -227,6 +234,13 @@ typedef struct {
   float ms;
 } lnr_kernel_time;
 lnr_status lnr_profile_enable(lnr_context *ctx, int enable);
+/* Failure injection for tests of the error paths: after `after` further
+ * device allocations through ctx succeed, the next one fails exactly as a
+ * failed hipMalloc does (LNR_E_OUT_OF_MEMORY; no device memory is taken), and
+ * injection then switches itself off.  after < 0 switches it off.  Every
+ * entry point must then return that status, free what it allocated and leave
+ * caller buffers untouched. */
+lnr_status lnr_debug_fail_allocation(lnr_context *ctx, int64_t after);
 lnr_status lnr_profile_read(lnr_context *ctx, lnr_kernel_time *out, int32_t max, int32_t *count);
 
 /* ---------------------------------------------------------------------------
@@ -265,12 +279,15 @@ typedef struct {
   int32_t superseded;       /* 1: replaced by a newer camera before it ran          */
   int32_t batch;            /* requests in the batch that computed it               */
   float batch_gpu_ms;       /* device time of that whole batch                      */
-  const float *rgb;         /* DEVICE float[3*H*W]; valid until the session's       */
-                            /* request after next completes                         */
+  const float *rgb;         /* DEVICE float[3*H*W]; the session's two output planes */
+                            /* alternate, so this stays valid until lnr_server_step */
+                            /* launches the session's request after next            */
   int32_t width, height;
 } lnr_server_result;
 /* The U-Net must have widths[0] <= 64 (its head is fused into the last
- * convolution, which lets one launch write every session's output). */
+ * convolution, which lets one launch write every session's output).
+ * lnr_server_open_session refuses (LNR_E_INVALID_ARG) a size whose
+ * floor(log2(min(width, height))) is below cfg->n_levels. */
 lnr_status lnr_server_create(lnr_context *ctx, const lnr_cloud *c, const lnr_unet *u, const lnr_server_config *cfg,
                              lnr_server **out);
 void lnr_server_destroy(lnr_server *srv); /* waits for its lanes; NULL-safe */

@@ -58,6 +58,8 @@ struct lnr_context {
   // caller may destroy objects in any order
   int children = 0;
   bool closed = false;
+  // lnr_debug_fail_allocation: device allocations left before one fails (-1: none)
+  int64_t fail_alloc_after = -1;
 };
 
 struct lnr_cloud {
@@ -139,6 +141,8 @@ const char *const kConvNames[2][6][2] = {
 lnr_status dalloc(lnr_context *ctx, void **p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 256;
+  if (ctx->fail_alloc_after >= 0 && ctx->fail_alloc_after-- == 0)
+    return fail(ctx, LNR_E_OUT_OF_MEMORY, "hipMalloc(" + std::to_string(bytes) + ") failed: injected failure");
   if (ctx->budget && ctx->allocated + bytes > ctx->budget)
     return fail(ctx, LNR_E_BUDGET,
                 "allocation of " + std::to_string(bytes) + " bytes exceeds the context budget of " +
@@ -271,6 +275,13 @@ float host_bf2f(uint16_t h) {
   std::memcpy(&f, &u, 4);
   return f;
 }
+// float32 -> IEEE binary16, round to nearest even (the compiler's conversion)
+uint16_t host_f2h(float f) {
+  const _Float16 h = (_Float16)f;
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
 
 
 // ---------------------------------------------------------------------------
@@ -290,7 +301,7 @@ UNetLayout unet_layout(const lnr_unet *u, int H, int W, int B) {
   y.H = H;
   y.W = W;
   y.B = B;
-  y.es = (u->prec == Prec::BF16) ? 2 : 4;
+  y.es = prec_half(u->prec) ? 2 : 4;
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   size_t off = 0;
   y.x0_bs = (size_t)H * W * u->cin0_pad;
@@ -670,6 +681,8 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   sc.z_near = cam->z_near;
   sc.z_far = cam->z_far;
   sc.W = (uint32_t)cam->width;
+  // every allocation comes before the first launch: a failure leaves the image untouched
+  if (soft && (st = ensure(ctx, scr.soft_acc, 16ull * npix)) != LNR_OK) return st;
   LNR_LAUNCH(ctx, "clear", s, launch_clear(out->key, npix, counters, s));
   LNR_LAUNCH(ctx, "cull", s, launch_cull(c->d, prm, static_cast<uint8_t *>(scr.flags.p), static_cast<uint2 *>(scr.chunks.p),
                            counters, s));
@@ -677,7 +690,6 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   LNR_LAUNCH(ctx, "splat", s,
              launch_splat(c->d, static_cast<const uint2 *>(scr.chunks.p), counters, sc, out->key, count, s));
   if (soft) {
-    if ((st = ensure(ctx, scr.soft_acc, 16ull * npix)) != LNR_OK) return st;
     LNR_LAUNCH(ctx, "soft", s,
                launch_soft(c->d, static_cast<const uint2 *>(scr.chunks.p), counters, sc, out->key, 1.0f + soft_eps,
                            static_cast<uint32_t *>(scr.soft_acc.p), out->depth, reinterpret_cast<uint32_t *>(out->rgba),
@@ -695,11 +707,13 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
 
 lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out, uint32_t flags,
                       void *hip_stream) {
+  if (!ctx) return LNR_E_INVALID_ARG;
   return render_impl(ctx, ctx->sc, c, cam, out, flags, false, 0.f, hip_stream);
 }
 
 lnr_status lnr_render_soft(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out,
                            float soft_eps, uint32_t flags, void *hip_stream) {
+  if (!ctx) return LNR_E_INVALID_ARG;
   return render_impl(ctx, ctx->sc, c, cam, out, flags, true, soft_eps, hip_stream);
 }
 
@@ -838,8 +852,9 @@ lnr_status lnr_unet_load(lnr_context *ctx, const void *blob_host, uint64_t bytes
   if (!ctx) return LNR_E_INVALID_ARG;
   if (!blob_host || !out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
   *out = nullptr;
-  if (prec != LNR_FP32 && prec != LNR_BF16 && prec != LNR_BF16X3)
+  if (prec != LNR_FP32 && prec != LNR_BF16 && prec != LNR_BF16X3 && prec != LNR_FP16 && prec != LNR_FP8_E4M3)
     return fail(ctx, LNR_E_INVALID_ARG, "unknown precision");
+  if (prec == LNR_FP8_E4M3) return fail(ctx, LNR_E_UNSUPPORTED, "LNR_FP8_E4M3 is not built");
   const uint8_t *p = static_cast<const uint8_t *>(blob_host);
   size_t off = 0;
   auto rd_u32 = [&](uint32_t *v) -> bool {
@@ -984,6 +999,10 @@ lnr_status lnr_unet_load(lnr_context *ctx, const void *blob_host, uint64_t bytes
           }
         if ((st = upload(wu.data(), 4 * wu.size(), &cl.wu)) != LNR_OK) return free_all(), st;
       }
+    } else if (u->prec == Prec::FP16) {
+      std::vector<uint16_t> h(np);
+      for (size_t i = 0; i < np; ++i) h[i] = host_f2h(packed[i]);
+      if ((st = upload(h.data(), 2 * np, &cl.w)) != LNR_OK) return free_all(), st;
     } else {
       std::vector<uint16_t> hi(np), lo(np);
       for (size_t i = 0; i < np; ++i) {
@@ -1046,6 +1065,12 @@ lnr_status lnr_sync(lnr_context *ctx, void *hip_stream) {
   if (st != LNR_OK) return st;
   LNR_HIP(ctx, hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
   LNR_HIP(ctx, hipGetLastError());
+  return LNR_OK;
+}
+
+lnr_status lnr_debug_fail_allocation(lnr_context *ctx, int64_t after) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  ctx->fail_alloc_after = after < 0 ? -1 : after;
   return LNR_OK;
 }
 
@@ -1255,6 +1280,13 @@ lnr_status lnr_server_open_session(lnr_server *srv, int32_t width, int32_t heigh
   if (width < 1 || height < 1 || width > srv->cfg.max_width || height > srv->cfg.max_height || width % a ||
       height % a)
     return fail(ctx, LNR_E_INVALID_ARG, "session size must be within the server's maximum and divisible by 2^(L-1)");
+  if (srv->cfg.n_levels > 0) {
+    int maxn = 0;
+    while ((2 << maxn) <= std::min(width, height)) ++maxn;
+    if (srv->cfg.n_levels > maxn)
+      return fail(ctx, LNR_E_INVALID_ARG,
+                  "the server's n_levels exceeds floor(log2(min(width, height))) of this session size");
+  }
   lnr_status st = use_device(ctx);
   if (st != LNR_OK) return st;
   const size_t np = (size_t)width * height;
@@ -1363,7 +1395,23 @@ lnr_status lnr_server_step(lnr_server *srv, int32_t *launched) {
   }
   const int B = (int)batch.size();
   hipStream_t s = lane->stream;
-  const bool was_profiling = ctx->profiling;
+  // On any failure below, undo what this step changed: the lane's output list,
+  // the sessions' output-plane toggles and the context's timing switch (no
+  // request is marked in flight before the end, so the batch stays pending).
+  struct Rollback {
+    lnr_server *srv;
+    ServerLane *lane;
+    const std::vector<int> &batch;
+    bool was_profiling;
+    std::vector<int> toggled;
+    bool armed = true;
+    ~Rollback() {
+      srv->ctx->profiling = was_profiling;
+      if (!armed) return;
+      lane->outs.clear();
+      for (int i : toggled) srv->sessions[i].next_out ^= 1;
+    }
+  } rb{srv, lane, batch, ctx->profiling, {}};
   ctx->profiling = false;
   LNR_HIP(ctx, hipEventRecord(lane->ev_start, s));
   const UNetLayout lay = unet_layout(srv->unet, H, W, B);
@@ -1374,12 +1422,10 @@ lnr_status lnr_server_step(lnr_server *srv, int32_t *launched) {
     if (st == LNR_OK && srv->cfg.n_levels > 0)
       st = depth_filter_impl(ctx, lane->sc, &img, srv->cfg.n_levels, srv->cfg.filter_strength, s);
     if (st == LNR_OK) st = unet_pack(ctx, lane->sc, srv->unet, lay, b, ss.depth, reinterpret_cast<const uint32_t *>(ss.rgba), s);
-    if (st != LNR_OK) {
-      ctx->profiling = was_profiling;
-      return st;
-    }
+    if (st != LNR_OK) return st;
     float *o = ss.out[ss.next_out];
     ss.next_out ^= 1;
+    rb.toggled.push_back(batch[b]);
     lane->head_outs_host[b] = o;
     lane->outs.push_back(o);
   }
@@ -1394,25 +1440,25 @@ lnr_status lnr_server_step(lnr_server *srv, int32_t *launched) {
       st = unet_convs(ctx, lane->sc, srv->unet, lay, nullptr, lane->head_outs_dev, s);
       hipError_t e = hipStreamEndCapture(s, &g);
       if (st != LNR_OK) {
-        ctx->profiling = was_profiling;
         if (g) (void)hipGraphDestroy(g);
         return st;
       }
       if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
-      LNR_HIP(ctx, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(ctx, e, "hipGraphInstantiate");
+      }
       lane->graph_defs.push_back(g);
       it = lane->graphs.emplace(key, ge).first;
     }
     LNR_HIP(ctx, hipGraphLaunch(it->second, s));
   } else {
     st = unet_convs(ctx, lane->sc, srv->unet, lay, nullptr, lane->head_outs_dev, s);
-    if (st != LNR_OK) {
-      ctx->profiling = was_profiling;
-      return st;
-    }
+    if (st != LNR_OK) return st;
   }
-  ctx->profiling = was_profiling;
   LNR_HIP(ctx, hipEventRecord(lane->ev_done, s));
+  rb.armed = false;
   for (int b = 0; b < B; ++b) {
     ServerSession &ss = srv->sessions[batch[b]];
     ss.pending = false;

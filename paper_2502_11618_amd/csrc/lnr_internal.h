@@ -114,7 +114,9 @@ hipError_t launch_upsample(int k, int n, const float *const *D, float *const *U,
                            float *depth, uint32_t *rgba, float fs, float one_plus_fs, hipStream_t s);
 
 // unet.hip
-enum class Prec { F32 = 0, BF16 = 1, BF16X3 = 2 };
+// values equal the public lnr_precision ones
+enum class Prec { F32 = 0, BF16 = 1, FP8 = 2, BF16X3 = 3, FP16 = 4 };
+inline bool prec_half(Prec p) { return p == Prec::BF16 || p == Prec::FP16; }
 
 struct ConvLayer {
   int cout = 0, cin = 0, k = 3;  // logical sizes

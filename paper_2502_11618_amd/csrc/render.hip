@@ -123,8 +123,8 @@ __device__ inline bool work_item(uint32_t i, const uint32_t *__restrict__ counte
   return false;
 }
 
-// One block per work item.  Keys only ever decrease, so a plain (possibly
-// stale) read of the pixel's key is an upper bound of its current value and
+// One block per work item.  Keys only ever decrease, so a (possibly stale)
+// relaxed read of the pixel's key is an upper bound of its current value and
 // the atomic can be skipped when the new key is not smaller.  COUNT adds the
 // number of atomics issued to counters[kAtomicWord] (one add per wave), for
 // measurement; the keys written are the same.
@@ -151,7 +151,8 @@ __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict
     if (!(u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf)) continue;
     const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | j;
     uint64_t *dst = key + (size_t)(uint32_t)v * cam.W + (uint32_t)u;
-    if (k < *dst) {
+    // relaxed atomic read: other lanes lower the word concurrently
+    if (k < __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       atomicMin(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)k);
       if constexpr (COUNT) ++issued;
     }

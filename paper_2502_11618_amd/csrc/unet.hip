@@ -15,6 +15,9 @@
 //          float32 accumulation, round-to-nearest-even to bfloat16 on store.
 //   BF16X3 float32 activations; operands split into bfloat16 hi + lo in LDS,
 //          hi*hi + hi*lo + lo*hi on the bf16 MFMA with float32 accumulation.
+//   FP16   float16 activations and weights, v_mfma_f32_32x32x16_f16, float32
+//          accumulation, round-to-nearest-even to float16 on store (the same
+//          data movement as BF16, with a 10- instead of a 7-bit fraction).
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -26,8 +29,10 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 __device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ inline f16x8 as_f16x8(uint4 v) { return __builtin_bit_cast(f16x8, v); }
 
 struct ConvArgs {
   const void *in0;
@@ -58,7 +63,8 @@ struct ConvArgs {
 //   MODE 0  float32 activations and weights, v_mfma_f32_32x32x2_f32;
 //   MODE 1  bf16 activations and weights, v_mfma_f32_32x32x16_bf16;
 //   MODE 2  float32 activations, each operand split into bf16 hi + lo in LDS
-//           (weights are stored split), product hi*hi + hi*lo + lo*hi.
+//           (weights are stored split), product hi*hi + hi*lo + lo*hi;
+//   MODE 3  fp16 activations and weights, v_mfma_f32_32x32x16_f16.
 // Workgroup tile: 4R rows x 32 columns of output pixels x BM output channels;
 // wave w owns rows [wR, wR + R).  Per staged chunk of CK input channels the
 // input tile with its halo and the chunk's weights ([co][tap][CK], one copy per
@@ -76,6 +82,23 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
   typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
   const floatx2 v = {lo, hi};
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));  // round to nearest even
+}
+__device__ inline uint32_t pack_f16x2(float lo, float hi) {
+  typedef float floatx2 __attribute__((ext_vector_type(2)));
+  typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+  const floatx2 v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));  // round to nearest even
+}
+// two float32 values -> the 16-bit storage format of MODE 1 (bf16) or MODE 3 (fp16)
+template <int MODE>
+__device__ inline uint32_t pack16x2(float lo, float hi) {
+  if constexpr (MODE == 3) return pack_f16x2(lo, hi);
+  else return pack_bf16x2(lo, hi);
+}
+template <int MODE>
+__device__ inline float unpack16(uint32_t bits16) {
+  if constexpr (MODE == 3) return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+  else return __uint_as_float(bits16 << 16);
 }
 
 template <int MODE>
@@ -104,6 +127,11 @@ struct ConvTraits<2> {  // float32 activations, split bf16 operands
   static constexpr int kInVec = 4, kWVec = 8;
   static constexpr int kPad = 8, kPlanes = 2, kGroup = 16;
 };
+template <>
+struct ConvTraits<3> : ConvTraits<1> {};  // fp16: bf16's data movement
+
+// 16-bit activations in HBM (bf16 or fp16)
+constexpr bool half_store(int mode) { return mode == 1 || mode == 3; }
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
@@ -181,8 +209,8 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         const float x0 = (float)(q & 255u) / 255.0f, x1 = (float)((q >> 8) & 255u) / 255.0f;
         const float x2 = (float)((q >> 16) & 255u) / 255.0f, x3 = A ? d * 0.0625f : 0.f, x4 = A ? 1.f : 0.f;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if constexpr (MODE == 1) {
-          if (qi == 0) v = make_uint4(pack_bf16x2(x0, x1), pack_bf16x2(x2, x3), pack_bf16x2(x4, 0.f), 0u);
+        if constexpr (half_store(MODE)) {
+          if (qi == 0) v = make_uint4(pack16x2<MODE>(x0, x1), pack16x2<MODE>(x2, x3), pack16x2<MODE>(x4, 0.f), 0u);
         } else if constexpr (MODE == 0) {
           // channels (x0, x1, x2, 0 | x3, x4, 0, 0): k-steps pair channel s
           // with channel 4 + s, so the fourth pair is zero and skipped
@@ -285,6 +313,9 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
           } else if constexpr (MODE == 1) {
             acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(f.a[0][mb][dy]), as_bf16x8(f.b[0][r + dy]),
                                                                  acc[mb][r], 0, 0, 0);
+          } else if constexpr (MODE == 3) {
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(f.a[0][mb][dy]), as_f16x8(f.b[0][r + dy]),
+                                                                acc[mb][r], 0, 0, 0);
           } else {
             const int P1 = T::kPlanes - 1;  // lo plane
             acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(f.a[P1][mb][dy]), as_bf16x8(f.b[0][r + dy]),
@@ -323,7 +354,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
       }
       // scheduler strategy for MFMA / LDS-read interleaving (measured: 1 for
       // bf16, 0 for the three-pass split mode)
-      if constexpr (MODE == 1) __builtin_amdgcn_iglp_opt(1);
+      if constexpr (half_store(MODE)) __builtin_amdgcn_iglp_opt(1);
       else __builtin_amdgcn_iglp_opt(0);
     }
   };
@@ -383,8 +414,8 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     return;
   }
   auto put4 = [&](InT *dst, const float (&v)[4]) {
-    if constexpr (MODE == 1)
-      *reinterpret_cast<uint2 *>(dst) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+    if constexpr (half_store(MODE))
+      *reinterpret_cast<uint2 *>(dst) = make_uint2(pack16x2<MODE>(v[0], v[1]), pack16x2<MODE>(v[2], v[3]));
     else
       *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
   };
@@ -395,7 +426,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   // channels, consecutive lanes covering consecutive memory.
   constexpr int PSTR = BM * 2 + 16;                              // staged bytes per pixel
   constexpr int STAGE = 4 * R * 32 * PSTR;                       // all waves
-  constexpr bool kStage = MODE == 1 && (STAGE <= (int)sizeof(s_in) || STAGE <= (int)sizeof(s_w));
+  constexpr bool kStage = half_store(MODE) && (STAGE <= (int)sizeof(s_in) || STAGE <= (int)sizeof(s_w));
   char *stage = nullptr;
   if constexpr (kStage) {
     __syncthreads();  // every wave is done with the K loop's LDS
@@ -419,7 +450,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
       for (int r = 0; r < R; ++r) {
         if constexpr (kStage) {
           *reinterpret_cast<uint2 *>(stage + (r * 32 + n) * PSTR + (mb * 32 + 8 * j + 4 * h) * 2) =
-              make_uint2(pack_bf16x2(v[r][0], v[r][1]), pack_bf16x2(v[r][2], v[r][3]));
+              make_uint2(pack16x2<MODE>(v[r][0], v[r][1]), pack16x2<MODE>(v[r][2], v[r][3]));
         } else {
           const int gy = ty0 + row0 + r;
           if (gy < H && gx < W) put4(out + ((size_t)gy * W + gx) * a.cout + c, v[r]);
@@ -857,9 +888,10 @@ __global__ __launch_bounds__(256) void pack_kernel(const float *__restrict__ dep
   v[2] = (float)((q >> 16) & 255u) / 255.0f;
   v[GAP ? 4 : 3] = A ? depth[p] * 0.0625f : 0.f;
   v[GAP ? 5 : 4] = A ? 1.f : 0.f;
-  if (MODE == 1) {  // cpad is 16: two 16-byte stores
+  if (half_store(MODE)) {  // cpad is 16: two 16-byte stores
     uint4 *o = reinterpret_cast<uint4 *>(static_cast<uint16_t *>(x) + (size_t)p * cpad);
-    o[0] = make_uint4(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]), pack_bf16x2(v[4], v[5]), pack_bf16x2(v[6], v[7]));
+    o[0] = make_uint4(pack16x2<MODE>(v[0], v[1]), pack16x2<MODE>(v[2], v[3]), pack16x2<MODE>(v[4], v[5]),
+                      pack16x2<MODE>(v[6], v[7]));
     o[1] = make_uint4(0u, 0u, 0u, 0u);
   } else {
     float *o = static_cast<float *>(x) + (size_t)p * cpad;
@@ -877,12 +909,12 @@ __global__ __launch_bounds__(256) void head_kernel(const void *__restrict__ x, i
   float y0 = b[0], y1 = b[1], y2 = b[2];
   for (int c = 0; c < C; c += 4) {
     float v[4];
-    if (MODE == 1) {
+    if (half_store(MODE)) {
       const uint2 q = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(x) + (size_t)p * C + c);
-      v[0] = __uint_as_float(q.x << 16);
-      v[1] = __uint_as_float(q.x & 0xFFFF0000u);
-      v[2] = __uint_as_float(q.y << 16);
-      v[3] = __uint_as_float(q.y & 0xFFFF0000u);
+      v[0] = unpack16<MODE>(q.x & 0xFFFFu);
+      v[1] = unpack16<MODE>(q.x >> 16);
+      v[2] = unpack16<MODE>(q.y & 0xFFFFu);
+      v[3] = unpack16<MODE>(q.y >> 16);
     } else {
       const float4 q = *reinterpret_cast<const float4 *>(static_cast<const float *>(x) + (size_t)p * C + c);
       v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
@@ -975,16 +1007,17 @@ hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s)
   if constexpr (MODE == 0) {
     if (ck == 8) return wide ? conv_launch<0, 64, 8, 2>(a, cout_pad, s) : conv_launch<0, 32, 8, 2>(a, cout_pad, s);
     return (wide && !small) ? conv_launch<0, 64, 16, 2>(a, cout_pad, s) : conv_launch<0, 32, 16, 2>(a, cout_pad, s);
-  } else if constexpr (MODE == 1) {
+  } else if constexpr (half_store(MODE)) {
     if (ck < 16) return hipErrorInvalidValue;
     if (wide && !small)
-      return ck == 32 ? conv_launch<1, 64, 32, 2>(a, cout_pad, s) : conv_launch<1, 64, 16, 2>(a, cout_pad, s);
+      return ck == 32 ? conv_launch<MODE, 64, 32, 2>(a, cout_pad, s) : conv_launch<MODE, 64, 16, 2>(a, cout_pad, s);
     if (wide)  // small grid: 32-channel workgroups, 2 rows per wave
-      return ck == 32 ? conv_launch<1, 32, 32, 2>(a, cout_pad, s) : conv_launch<1, 32, 16, 2>(a, cout_pad, s);
+      return ck == 32 ? conv_launch<MODE, 32, 32, 2>(a, cout_pad, s) : conv_launch<MODE, 32, 16, 2>(a, cout_pad, s);
     if (a.C0 + a.C1 > 32)
-      return ck == 32 ? conv_launch<1, 32, 32, 4>(a, cout_pad, s) : conv_launch<1, 32, 16, 4>(a, cout_pad, s);
+      return ck == 32 ? conv_launch<MODE, 32, 32, 4>(a, cout_pad, s) : conv_launch<MODE, 32, 16, 4>(a, cout_pad, s);
     // the layer with the fused head: 16-channel chunks measured faster (the same sums in the same order)
-    return ck == 32 && !head ? conv_launch<1, 32, 32, 2>(a, cout_pad, s) : conv_launch<1, 32, 16, 2>(a, cout_pad, s);
+    return ck == 32 && !head ? conv_launch<MODE, 32, 32, 2>(a, cout_pad, s)
+                             : conv_launch<MODE, 32, 16, 2>(a, cout_pad, s);
   } else {
     if (ck < 16) return hipErrorInvalidValue;
     if (wide) return conv_launch<2, 64, 16, 2>(a, cout_pad, s);
@@ -1000,6 +1033,8 @@ hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, in
   const int nb = (npix + 255) / 256;
   if (p == Prec::BF16)
     pack_kernel<1, false><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
+  else if (p == Prec::FP16)
+    pack_kernel<3, false><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
   else if (p == Prec::F32)
     pack_kernel<0, true><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
   else
@@ -1026,6 +1061,8 @@ hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s) {
     case Prec::F32: return conv_dispatch<0>(a, ck, L.cout_pad, s);
     case Prec::BF16: return conv_dispatch<1>(a, ck, L.cout_pad, s);
     case Prec::BF16X3: return conv_dispatch<2>(a, ck, L.cout_pad, s);
+    case Prec::FP16: return conv_dispatch<3>(a, ck, L.cout_pad, s);
+    default: break;
   }
   return hipErrorInvalidValue;
 }
@@ -1036,6 +1073,8 @@ hipError_t launch_head(const void *x, int C, int H, int W, const ConvLayer &head
   const float *w = static_cast<const float *>(head.w);
   if (p == Prec::BF16)
     head_kernel<1><<<nb, 256, 0, s>>>(x, C, npix, w, head.bias, out);
+  else if (p == Prec::FP16)
+    head_kernel<3><<<nb, 256, 0, s>>>(x, C, npix, w, head.bias, out);
   else
     head_kernel<0><<<nb, 256, 0, s>>>(x, C, npix, w, head.bias, out);
   return hipGetLastError();

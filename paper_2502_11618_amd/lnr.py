@@ -27,7 +27,9 @@ LNR_E_FORMAT = -6
 
 LNR_FP32 = 0
 LNR_BF16 = 1
-LNR_BF16X3 = 2
+LNR_FP8_E4M3 = 2
+LNR_BF16X3 = 3
+LNR_FP16 = 4
 
 LNR_RENDER_NO_CULL = 1
 LNR_RENDER_COUNT_ATOMICS = 2
@@ -117,6 +119,7 @@ def _load():
         "lnr_reconstruct": (i32, [vp, vp, ctypes.POINTER(lnr_image), vp, vp]),
         "lnr_sync": (i32, [vp, vp]),
         "lnr_profile_enable": (i32, [vp, ctypes.c_int]),
+        "lnr_debug_fail_allocation": (i32, [vp, ctypes.c_int64]),
         "lnr_profile_read": (i32, [vp, ctypes.POINTER(lnr_kernel_time), i32, ctypes.POINTER(i32)]),
         "lnr_server_create": (i32, [vp, vp, vp, ctypes.POINTER(lnr_server_config), ctypes.POINTER(vp)]),
         "lnr_server_destroy": (None, [vp]),
@@ -367,6 +370,11 @@ def lnr_sync(ctx: Context, stream=None) -> None:
 
 def lnr_profile_enable(ctx: Context, enable: bool = True) -> None:
     _check(_lib.lnr_profile_enable(ctx.handle, 1 if enable else 0), ctx.handle)
+
+
+def lnr_debug_fail_allocation(ctx: Context, after: int) -> None:
+    """Make the device allocation after `after` successful ones fail (-1: off)."""
+    _check(_lib.lnr_debug_fail_allocation(ctx.handle, int(after)), ctx.handle)
 
 
 def lnr_profile_read(ctx: Context, max_records: int = 1 << 16):

@@ -17,13 +17,12 @@ from oracle import grid as G
 from oracle import metrics as M
 from oracle import render as R
 from oracle import unet as U
-from tests.gpu_util import assert_images_equal, image_from_host, image_to_host, render_gpu
+from tests.gpu_util import FP32, UNET_PRECISIONS, check_unet_error, assert_images_equal, image_from_host, image_to_host, render_gpu
 
 pytestmark = pytest.mark.gpu
 
 W, H, FOV, NL, FS, CELL = 3840, 2160, 90.0, 6, 0.5, 1.0
 WIDTHS = (32, 64, 128, 256, 512)
-BOUND = {0: 1e-4, 1: 8e-2, 2: 2e-2}
 WINDOWS = [(0, 64, 0, 64), (H - 64, H, W - 64, W), (1000, 1064, 2901, 2965)]
 
 
@@ -52,7 +51,7 @@ def test_4k_render_and_six_level_filter_bit_exact(lnr, ctx, four_k):
     assert_images_equal((None, gd, gr), (None, fd, fr), "4k filter")
 
 
-@pytest.mark.parametrize("prec", [0, 2, 1])
+@pytest.mark.parametrize("prec", UNET_PRECISIONS)
 def test_4k_five_level_unet_sampled_windows(lnr, ctx, four_k, prec):
     import torch
     _, _, _, fd, fr = four_k["oracle"]
@@ -62,7 +61,7 @@ def test_4k_five_level_unet_sampled_windows(lnr, ctx, four_k, prec):
     torch.cuda.synchronize()
     got = out.cpu().numpy().astype(np.float64)
     worst = max(M.max_abs(got[:, a:b, c:d], ref) for (a, b, c, d), ref in zip(WINDOWS, four_k["refs"]))
-    assert worst <= BOUND[prec], f"prec {prec}: worst max-abs {worst}"
+    check_unet_error(prec, worst, "4k windows")
 
 
 def test_4k_batch_of_eight_views_equals_alone(lnr, ctx, four_k):

@@ -19,13 +19,12 @@ from oracle import grid as G
 from oracle import metrics as M
 from oracle import render as R
 from oracle import unet as U
-from tests.gpu_util import assert_images_equal, image_from_host, image_to_host, render_gpu
+from tests.gpu_util import FP32, UNET_PRECISIONS, check_unet_error, assert_images_equal, image_from_host, image_to_host, render_gpu
 
 pytestmark = pytest.mark.gpu
 
 W, H, FOV, NL, FS, CELL = 1920, 1080, 90.0, 5, 0.5, 1.0
 WIDTHS = (32, 64, 128, 256)
-BOUND = {0: 1e-4, 1: 8e-2, 2: 2e-2}
 FRAMES = (0, 30, 60, 90)
 UNET_FRAMES = (0, 60)
 
@@ -73,7 +72,7 @@ def test_fullsize_render_and_filter_bit_exact(lnr, ctx, full):
         assert_images_equal((None, gd, gr), (None, fd, fr), f"filter frame {f}")
 
 
-@pytest.mark.parametrize("prec", [0, 2, 1])
+@pytest.mark.parametrize("prec", UNET_PRECISIONS)
 def test_fullsize_unet_sampled_windows(lnr, ctx, full, prec):
     import torch
     net = lnr.lnr_unet_load(ctx, full["blob"], prec)
@@ -87,10 +86,10 @@ def test_fullsize_unet_sampled_windows(lnr, ctx, full, prec):
         got = out.cpu().numpy().astype(np.float64)
         for (a, b, c, d), ref in zip(_windows(f), _refs(full, f)):
             worst = max(worst, M.max_abs(got[:, a:b, c:d], ref))
-    assert worst <= BOUND[prec], f"prec {prec}: worst max-abs {worst} over sampled windows"
+    check_unet_error(prec, worst, "1080p windows")
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 4])
 def test_fullsize_batched_serving_equals_alone(lnr, ctx, full, prec):
     import torch
     net = lnr.lnr_unet_load(ctx, full["blob"], prec)

@@ -118,18 +118,41 @@ def test_input_tensor_definition():
     assert np.all(x[0, 1] == 0)
 
 
-def test_crop_reproduces_full_image_interior():
-    blob = synth.make_unet_blob((4, 8, 8), seed=2, bias="uniform")
+@pytest.mark.parametrize("widths,H,W", [
+    ((4, 8, 8), 96, 128),
+    # the depths the full-size (4 levels) and 4K (5 levels) GPU tests compare on crops
+    ((4, 6, 8, 8), 176, 208),
+    ((4, 4, 6, 6, 8), 352, 384),
+])
+def test_crop_reproduces_full_image_interior(widths, H, W):
+    """forward_crop (a crop grown by receptive_margin and aligned to 2^(L-1))
+    equals the full-image forward pass on windows at the corners, the edges
+    and the interior; with half the margin the interior window differs, so the
+    comparison would catch a margin that is too small."""
+    L = len(widths)
+    blob = synth.make_unet_blob(widths, seed=2, bias="uniform")
     net = U.parse_blob(blob)
-    rng = np.random.default_rng(3)
-    H, W = 96, 128
+    rng = np.random.default_rng(3 + L)
     depth = rng.uniform(0.5, 10, (H, W)).astype(np.float32)
     rgba = rng.integers(0, 256, (H, W, 4)).astype(np.uint8)
     rgba[..., 3] = rng.random((H, W)) < 0.7
     full = U.forward(net, depth, rgba)
-    for (y0, y1, x0, x1) in [(40, 48, 50, 70), (0, 8, 0, 16), (90, 96, 120, 128)]:
+    m = U.receptive_margin(L)
+    assert min(H, W) > 2 * m + 16  # the interior window has a real crop around it
+    windows = [(0, 8, 0, 16), (H - 6, H, W - 8, W), (0, 16, W - 16, W), (H - 16, H, 0, 16),
+               (H // 2 - 3, H // 2 + 5, W // 2 - 7, W // 2 + 9)]
+    for (y0, y1, x0, x1) in windows:
         part = U.forward_crop(net, depth, rgba, y0, y1, x0, x1)
-        assert np.max(np.abs(part - full[:, y0:y1, x0:x1])) < 1e-12
+        assert np.max(np.abs(part - full[:, y0:y1, x0:x1])) < 1e-12, (L, y0, x0)
+    if L >= 4:
+        y0, y1, x0, x1 = windows[-1]
+        orig = U.receptive_margin
+        try:
+            U.receptive_margin = lambda levels: orig(levels) // 2
+            part = U.forward_crop(net, depth, rgba, y0, y1, x0, x1)
+        finally:
+            U.receptive_margin = orig
+        assert np.max(np.abs(part - full[:, y0:y1, x0:x1])) > 1e-9
 
 
 def test_parser_rejects_bad_blobs():
@@ -140,10 +163,27 @@ def test_parser_rejects_bad_blobs():
         U.parse_blob(blob + b"\0")
 
 
-def test_flop_count_formula():
-    net = U.parse_blob(synth.make_unet_blob((32, 64, 128, 256), seed=0))
-    # per full-resolution pixel: sum over convs of 2 * c_out * c_in * k^2 / 4^level
-    assert U.flops_per_pixel(net) == 2 * (32 * 5 * 9 + 32 * 32 * 9 + 32 * 96 * 9 + 32 * 32 * 9 + 3 * 32
-                                          + (64 * 32 * 9 + 64 * 64 * 9 + 64 * 192 * 9 + 64 * 64 * 9) / 4
-                                          + (128 * 64 * 9 + 128 * 128 * 9 + 128 * 384 * 9 + 128 * 128 * 9) / 16
-                                          + (256 * 128 * 9 + 256 * 256 * 9) / 64)
+def test_flop_count_matches_the_convolutions_a_forward_pass_runs(monkeypatch):
+    """flops_per_pixel x H x W equals 2 x the multiply-adds of the convolutions
+    that a forward pass actually calls, counted from their operand shapes."""
+    widths = (4, 8, 12, 16)
+    net = U.parse_blob(synth.make_unet_blob(widths, seed=0))
+    H, W = 48, 64
+    macs = []
+    c3, c1 = U.conv3x3, U.conv1x1
+
+    def count3(x, c):
+        macs.append(x.shape[0] * x.shape[1] * c.W.shape[0] * c.W.shape[1] * 9)
+        return c3(x, c)
+
+    def count1(x, c):
+        macs.append(x.shape[0] * x.shape[1] * c.W.shape[0] * c.W.shape[1])
+        return c1(x, c)
+
+    monkeypatch.setattr(U, "conv3x3", count3)
+    monkeypatch.setattr(U, "conv1x1", count1)
+    depth = np.ones((H, W), np.float32)
+    rgba = np.ones((H, W, 4), np.uint8)
+    U.forward(net, depth, rgba)
+    assert len(macs) == 4 * len(widths) - 1
+    assert U.flops_per_pixel(net) * H * W == 2 * sum(macs)
