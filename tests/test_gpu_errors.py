@@ -96,7 +96,11 @@ def test_render_filter_reconstruct_leave_outputs_untouched(lnr, room_cloud, room
     for _ in _sweep(lnr, ctx, render):
         assert _untouched(img), "a failed render wrote the image"
         fails += 1
-    assert fails >= 3
+    # the context's scratch is grow-only and kept: after the n-th allocation
+    # fails, the ones before it stay, so the next attempt starts further on
+    # (hard: flags, work queues, counters -> 2 failing attempts; soft adds the
+    # colour sums -> 3)
+    assert fails >= (3 if soft else 2)
     fimg = _sentinel_image(lnr, H, W)
     fimg.key = None
     for _ in _sweep(lnr, ctx, lambda: lnr.lnr_depth_filter(ctx, fimg, 4, 0.5)):
