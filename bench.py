@@ -31,8 +31,8 @@ if ROOT not in sys.path:
 
 METRIC = "frames/s and p50/p99 latency at 1080p/20M pts; BF16 vs FP32 U-Net at stated PSNR"
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
-TOL = {"fp32": 1e-4, "bf16": 2e-2, "bf16x3": 2e-2}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
+TOL = {"fp32": 1e-4, "bf16": 2e-2, "bf16x3": 2e-2, "fp16": 2e-2}
 
 
 def log(*a):
@@ -53,26 +53,27 @@ def conv_shapes(widths, H, W, cin0):
 
 
 def algorithmic_bytes(H, W, n_levels, n_proc, n_filled, n_removed):
-    """Bytes each geometric kernel must move (reads + writes), per launch."""
+    """Bytes each geometric kernel must move (reads + writes), per launch:
+    clear 8 B per pixel (the key); splat 12 B per processed point (xyz);
+    resolve 8 B per pixel read (key) + 8 B written (depth, rgba) + 4 B per
+    filled pixel (its colour); pyramid 8 B per pixel read (depth, rgba) + 4 B
+    per pixel of every coarser level written; the fused upsample 8 B per pixel
+    read + 4 B per pixel of every coarser level read + 8 B per removed pixel
+    written."""
     P = H * W
     sizes = [(H, W)]
     for _ in range(n_levels):
         h, w = sizes[-1]
         sizes.append(((h + 1) // 2, (w + 1) // 2))
     px = [h * w for h, w in sizes]
-    b = {
+    coarse = 4 * sum(px[1:])
+    return {
         "clear": 8 * P,
         "splat": 12 * n_proc,
         "resolve": 8 * P + 8 * P + 4 * n_filled,
-        "pyramid": 8 * P + 4 * sum(px[1:]),
+        "pyramid": 8 * P + coarse,
+        "upsample": 8 * P + coarse + 8 * n_removed,
     }
-    for k in range(n_levels - 1, 0, -1):
-        uc = px[k + 1] * (1 if k + 1 == n_levels else 2)
-        b[f"upsample/k{k}"] = 4 * px[k] + 4 * px[k + 1] + 4 * uc + 4 * px[k]
-    if n_levels:
-        uc = px[1] * (1 if n_levels == 1 else 2)
-        b["upsample/k0"] = 8 * P + 4 * px[1] + 4 * uc + 8 * n_removed
-    return b
 
 
 def host_info():
@@ -92,17 +93,22 @@ def host_info():
 
 
 def cpu_baseline(scene, cam, blob, n_levels, fs, widths):
-    """The CPU oracle as it stands, on a bounded sample of the workload."""
+    """The CPU oracle as it stands, on a bounded sample of the workload: the
+    projection + resolve + depth filter of frame 0 over all points (numpy, one
+    thread), and the float64 U-Net on a centre crop, once with one BLAS thread
+    and once with every core, scaled by pixel count to the full frame (a full
+    1080p frame takes several minutes in float64, so the U-Net leg is
+    extrapolated and flagged as such)."""
     import numpy as np
     from oracle import depth_filter as F
     from oracle import grid as G
     from oracle import render as R
     from oracle import unet as U
     try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        all_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
-        blas_threads = 1
+        threadpool_limits, all_threads = None, 1
     g = G.partition(scene.xyz, scene.rgb, 1.0)
     t0 = time.perf_counter()
     _, depth, rgba = R.render(g, cam)
@@ -110,20 +116,35 @@ def cpu_baseline(scene, cam, blob, n_levels, fs, widths):
     fd, fr, _ = F.depth_filter(depth.reshape(H, W), rgba.reshape(H, W, 4), n_levels, fs)
     t_geo = time.perf_counter() - t0
     net = U.parse_blob(blob)
-    c = 128
-    y0, x0 = H // 2 - c // 2, W // 2 - c // 2
-    t0 = time.perf_counter()
-    U.forward(net, fd[y0:y0 + c, x0:x0 + c], fr[y0:y0 + c, x0:x0 + c])
-    t_unet_crop = time.perf_counter() - t0
-    t_unet = t_unet_crop * (H * W) / (c * c)
-    fps = 1.0 / (t_geo + t_unet)
+
+    def unet_crop(c):
+        y0, x0 = H // 2 - c // 2, W // 2 - c // 2
+        t = time.perf_counter()
+        U.forward(net, fd[y0:y0 + c, x0:x0 + c], fr[y0:y0 + c, x0:x0 + c])
+        return time.perf_counter() - t
+
+    c_all, c_one = 256, 96
+    t_all = unet_crop(c_all)
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t_one = unet_crop(c_one)
+    else:  # pragma: no cover
+        t_one = float("nan")
+    s_all = t_all * (H * W) / (c_all * c_all)
+    s_one = t_one * (H * W) / (c_one * c_one)
     return {
-        "value": round(fps, 6), "unit": "frames/s", "cores": int(blas_threads), "kind": "oracle",
+        "value": round(1.0 / (t_geo + s_all), 6), "unit": "frames/s", "cores": int(all_threads), "kind": "oracle",
+        "extrapolated": True,
         "sample": (f"frame 0 of the path: oracle projection + resolve + depth filter over all {scene.n} points "
-                   f"({t_geo:.2f} s, single-threaded numpy), plus the float64 U-Net on a {c}x{c} crop "
-                   f"({t_unet_crop:.2f} s, BLAS threads {blas_threads}) scaled by pixel count to {W}x{H} "
-                   f"({t_unet:.1f} s)"),
-        "seconds_per_frame": round(t_geo + t_unet, 3),
+                   f"({t_geo:.2f} s measured, one thread), plus the float64 U-Net on a {c_all}x{c_all} centre crop "
+                   f"({t_all:.2f} s with {all_threads} BLAS threads) scaled by pixel count to {W}x{H} "
+                   f"({s_all:.1f} s extrapolated)"),
+        "seconds_per_frame": round(t_geo + s_all, 3),
+        "legs": {"geometry_s": round(t_geo, 3), "geometry_threads": 1,
+                 "unet_all_cores_s": round(s_all, 1), "unet_all_cores_threads": int(all_threads),
+                 "unet_all_cores_crop": c_all,
+                 "unet_one_thread_s": round(s_one, 1), "unet_one_thread_crop": c_one,
+                 "frames_per_s_one_thread": round(1.0 / (t_geo + s_one), 6)},
     }
 
 
@@ -505,7 +526,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--points", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precisions", default="fp32,bf16x3,bf16")
+    ap.add_argument("--precisions", default="fp32,fp16,bf16x3,bf16")
     ap.add_argument("--no-error-check", action="store_true", help="skip the float64 error windows")
     ap.add_argument("--pipelined", action="store_true",
                     help="overlap the next frame's projection and filter (second stream and context) with the "
@@ -566,7 +587,7 @@ def main():
     load_s = time.perf_counter() - t0
     info = L.lnr_cloud_info(cloud)
     log(f"cloud loaded and partitioned in {load_s:.2f} s, grid {info['dims']}")
-    prec_ids = {"fp32": L.LNR_FP32, "bf16": L.LNR_BF16, "bf16x3": L.LNR_BF16X3}
+    prec_ids = {"fp32": L.LNR_FP32, "bf16": L.LNR_BF16, "bf16x3": L.LNR_BF16X3, "fp16": L.LNR_FP16}
     precs = [p for p in args.precisions.split(",") if p]
     nets = {p: L.lnr_unet_load(ctx, blob, prec_ids[p]) for p in precs}
     img = L.Image(H, W)
@@ -657,7 +678,17 @@ def main():
         log(f"{p}: {results[p]['frames_per_s']:.1f} frames/s, p50 {results[p]['latency_ms']['p50']:.2f} ms, "
             f"p99 {results[p]['latency_ms']['p99']:.2f} ms")
 
-    # geometric-stage statistics of frame 0 (filled / removed pixels) for the byte counts
+    # per-frame statistics of the timed frames (an untimed pass): processed
+    # points, filled pixels after projection and pixels kept by the filter
+    per_frame = {"processed_points": [], "filled_pixels": [], "kept_pixels": []}
+    for i in range(args.steps):
+        L.lnr_render(ctx, cloud, cams[i % len(cams)], img)
+        torch.cuda.synchronize()
+        per_frame["processed_points"].append(int(L.lnr_render_stats(ctx)[1]))
+        per_frame["filled_pixels"].append(int((img.rgba[..., 3] != 0).sum().item()))
+        L.lnr_depth_filter(ctx, img, NL, FS)
+        per_frame["kept_pixels"].append(int((img.rgba[..., 3] != 0).sum().item()))
+    # frame 0 again, for the error windows and the byte counts
     L.lnr_render(ctx, cloud, cams[0], img)
     torch.cuda.synchronize()
     _, proc0, _ = L.lnr_render_stats(ctx)
@@ -683,68 +714,81 @@ def main():
     atomic_rate, atomic_ops = L.lnr_measure_atomic_min(ctx, H * W, 0, 1 << 26)
     atomic_rate_contended, _ = L.lnr_measure_atomic_min(ctx, H * W, 1, 1 << 26)
 
-    # rooflines
+    # rooflines.  The float32 layers past the first run as Winograd F(2x2, 3x3):
+    # the matrix cores execute 16 multiplies per 2x2 output block and channel
+    # pair instead of the direct convolution's 36, and the first layer
+    # multiplies 6 of its 8 staged channels (3 k-pairs) per tap.  `frac` is the
+    # executed flops' share of the matrix peak (how busy the matrix cores
+    # are); `effective_tflops` is the direct convolution's algorithmic flops
+    # per second, which a Winograd kernel can push past the peak.
     p0 = precs[0]
     ks = kernel_stats[p0]
     cin0 = 8
     shapes = conv_shapes(widths, H, W, cin0)
     flops = {name: 2.0 * h * w * co * 9 * ci for (name, h, w, co, ci) in shapes}
-    # float32 layers past the first run as Winograd F(2x2, 3x3): 16 multiplies
-    # per 2x2 output block and channel pair on the matrix cores (direct: 36);
-    # the first layer multiplies 6 of its 8 staged channels (3 k-pairs) per tap
     mfma_flops = {name: (2.0 * ((h + 1) // 2) * ((w + 1) // 2) * 16 * co * ci if i > 0 else 2.0 * h * w * co * 9 * 6)
                   for i, (name, h, w, co, ci) in enumerate(shapes)}
-    conv_ms = {k: v[0] for k, v in ks.items() if k.startswith("conv/")}
-    dom = max(conv_ms, key=conv_ms.get)
-    achieved = flops[dom] / (conv_ms[dom] * 1e-3) / 1e12
-    executed = mfma_flops[dom] / (conv_ms[dom] * 1e-3) / 1e12
-    traffic = recorded_traffic(dom)
-    roofline = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["fp32"],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp32"], 4),
-                "traffic": None if traffic is None else round(traffic),
-                "flops_per_launch": flops[dom], "avg_launch_ms": round(conv_ms[dom], 4),
-                "algorithm": "winograd F(2x2,3x3)" if mfma_flops[dom] != flops[dom] else "direct",
-                "mfma_flops_per_launch": mfma_flops[dom], "mfma_achieved": round(executed, 2),
-                "mfma_frac": round(executed / PEAK_TFLOPS["fp32"], 4)}
-    unet_ms = sum(v[0] for k, v in ks.items() if k.startswith("conv/") or k in ("pack", "head"))
-    unet_flops = sum(flops.values()) + 2.0 * H * W * 3 * widths[0]
-    unet_mfma_flops = sum(mfma_flops.values()) + 2.0 * H * W * 3 * widths[0]
+    head_flops = 2.0 * H * W * 3 * widths[0]
+
+    def conv_roofline(kstats, prec, executed):
+        conv_ms = {k: v[0] for k, v in kstats.items() if k.startswith("conv/")}
+        dom = max(conv_ms, key=conv_ms.get)
+        peak = PEAK_TFLOPS[prec]
+        ex = executed[dom] / (conv_ms[dom] * 1e-3) / 1e12
+        eff = flops[dom] / (conv_ms[dom] * 1e-3) / 1e12
+        return dom, {"kernel": dom, "bound": "mfma", "achieved": round(ex, 2), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(ex / peak, 4), "flops_per_launch": executed[dom],
+                     "avg_launch_ms": round(conv_ms[dom], 4),
+                     "algorithm": "winograd F(2x2,3x3)" if executed[dom] != flops[dom] else "direct",
+                     "algorithmic_flops_per_launch": flops[dom], "effective_tflops": round(eff, 2)}
+
+    exec_fp32 = mfma_flops if p0 == "fp32" else flops
+    dom, roofline = conv_roofline(ks, p0, exec_fp32)
+    traffic = recorded_traffic(dom) if p0 == "fp32" else None
+    roofline["traffic"] = None if traffic is None else round(traffic)
+    unet_flops = sum(flops.values()) + head_flops
     n_proc = results[p0].get("processed_points_per_frame", proc0)
     gbytes = algorithmic_bytes(H, W, NL, n_proc, filled0, filled0 - kept0)
     geo_names = [k for k in ks if k in gbytes]
     geo_ms = sum(ks[k][0] for k in geo_names)
     geo_bytes = sum(gbytes[k] for k in geo_names)
     geo_gbs = geo_bytes / (geo_ms * 1e-3) / 1e9
-    splat_gbs = gbytes["splat"] / (ks["splat"][0] * 1e-3) / 1e9
     rooflines = {
-        "unet_fp32_all_convs": {"bound": "mfma", "achieved": round(unet_flops / (unet_ms * 1e-3) / 1e12, 2),
-                                "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
-                                "frac": round(unet_flops / (unet_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4),
-                                "mfma_frac": round(unet_mfma_flops / (unet_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
-                                                   4)},
         "render_and_filter": {"bound": "hbm", "achieved": round(geo_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                               "frac": round(geo_gbs / PEAK_HBM_GBS, 4), "bytes_per_frame": geo_bytes,
-                              "ms_per_frame": round(geo_ms, 4)},
-        "splat": {"bound": "hbm", "achieved": round(splat_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                  "frac": round(splat_gbs / PEAK_HBM_GBS, 4), "points_per_launch": n_proc,
-                  "avg_launch_ms": round(ks["splat"][0], 4),
-                  "points_per_s": round(n_proc / (ks["splat"][0] * 1e-3), 1)},
-        "splat_atomics": {"bound": "atomic", "achieved": round(float(np.mean(n_atomics)) / (ks["splat"][0] * 1e-3), 1),
-                          "peak": round(atomic_rate, 1), "unit": "atomics/s",
-                          "frac": round(float(np.mean(n_atomics)) / (ks["splat"][0] * 1e-3) / atomic_rate, 4),
-                          "atomics_per_frame": round(float(np.mean(n_atomics)), 1),
-                          "peak_kind": f"measured: {atomic_ops} 64-bit atomicMin on pseudo-random words of a "
-                                       f"{W}x{H} buffer",
-                          "contended_peak": round(atomic_rate_contended, 1)},
+                              "ms_per_frame": round(geo_ms, 4), "kernels": geo_names},
     }
-    for p in precs[1:]:
+    for k in ("splat", "bin", "tile"):
+        if k in ks and k in gbytes:
+            gbs = gbytes[k] / (ks[k][0] * 1e-3) / 1e9
+            rooflines[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                            "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": gbytes[k],
+                            "avg_launch_ms": round(ks[k][0], 4)}
+    if "splat" in ks and n_atomics:
+        rate = float(np.mean(n_atomics)) / (ks["splat"][0] * 1e-3)
+        rooflines["splat_atomics"] = {
+            "bound": "atomic", "achieved": round(rate, 1), "peak": round(atomic_rate, 1), "unit": "atomics/s",
+            "frac": round(rate / atomic_rate, 4), "atomics_per_frame": round(float(np.mean(n_atomics)), 1),
+            "peak_kind": f"measured: {atomic_ops} 64-bit atomicMin on pseudo-random words of a {W}x{H} buffer",
+            "contended_peak": round(atomic_rate_contended, 1)}
+    for p in precs:
         kp = kernel_stats[p]
         ms = sum(v[0] for k, v in kp.items() if k.startswith("conv/") or k in ("pack", "head"))
-        mult = 3.0 if p == "bf16x3" else 1.0
+        peak = PEAK_TFLOPS["fp32" if p == "fp32" else "bf16"]
+        if p == "fp32":
+            ex = sum(mfma_flops.values()) + head_flops
+        elif p == "bf16x3":
+            ex = 3.0 * unet_flops  # three bf16 passes per product
+        else:
+            ex = unet_flops
         rooflines[f"unet_{p}_all_convs"] = {
-            "bound": "mfma", "achieved": round(unet_flops / (ms * 1e-3) / 1e12, 2), "peak": PEAK_TFLOPS["bf16"],
-            "unit": "TFLOP/s", "frac": round(unet_flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"], 4),
-            "mfma_passes_per_product": mult}
+            "bound": "mfma", "achieved": round(ex / (ms * 1e-3) / 1e12, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(ex / (ms * 1e-3) / 1e12 / peak, 4), "executed_flops_per_frame": ex,
+            "effective_tflops": round(unet_flops / (ms * 1e-3) / 1e12, 2), "ms_per_frame": round(ms, 4)}
+        if p != p0:
+            rooflines[f"dominant_{p}_kernel"] = conv_roofline(kp, "fp32" if p == "fp32" else "bf16",
+                                                              {k: (3.0 * v if p == "bf16x3" else v)
+                                                               for k, v in flops.items()})[1]
 
     fps = results[p0]["frames_per_s"]
     line = {
@@ -762,19 +806,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": "multiroom-20M-pts-1920x1080-orbit120", "points": scene.n, "scans": 4,
                    "cell_m": 1.0, "width": W, "height": H, "fov_deg": FOV, "n_levels": NL, "filter_strength": FS,
-                   "unet_widths": list(widths), "frames": len(cams), "grid_dims": list(info["dims"]),
-                   "pipelined": bool(args.pipelined)},
+                   "unet_widths": list(widths), "path_frames": len(cams), "timed_frames": args.steps,
+                   "grid_dims": list(info["dims"]), "pipelined": bool(args.pipelined)},
         "latency_ms": {k: round(v, 4) for k, v in results[p0]["latency_ms"].items()},
         "points_per_s": round(n_proc * fps, 1),
         "processed_points_per_frame": round(n_proc, 1),
         "precisions": {p: {"frames_per_s": round(r["frames_per_s"], 3), "ms_per_frame": round(r["ms_per_frame"], 4),
                            "latency_ms": {k: round(v, 4) for k, v in r["latency_ms"].items()},
                            "error_vs_fp64_sampled": errors[p]} for p, r in results.items()},
+        "half_precision_within_bound": {
+            p: {"frames_per_s": round(results[p]["frames_per_s"], 3), "max_abs": errors[p]["max_abs"],
+                "bound": errors[p]["bound"]}
+            for p in precs if p != "fp32" and errors.get(p) and errors[p]["within_bound"]},
         "stage_ms": {p: {k: round(v[0], 4) for k, v in sorted(kernel_stats[p].items())} for p in precs},
         "roofline": roofline,
         "rooflines": rooflines,
         "load_partition_s": round(load_s, 3),
         "frame0": {"processed_points": proc0, "filled_pixels": filled0, "kept_after_filter": kept0},
+        "per_frame": per_frame,
         "env": host_info(),
     }
     try:

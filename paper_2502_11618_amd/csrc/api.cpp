@@ -128,10 +128,6 @@ hipEvent_t get_event(lnr_context *ctx) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, nm);                         \
   } while (0)
 
-const char *const kUpsampleNames[16] = {"upsample/k0",  "upsample/k1",  "upsample/k2",  "upsample/k3",
-                                        "upsample/k4",  "upsample/k5",  "upsample/k6",  "upsample/k7",
-                                        "upsample/k8",  "upsample/k9",  "upsample/k10", "upsample/k11",
-                                        "upsample/k12", "upsample/k13", "upsample/k14", "upsample/k15"};
 const char *const kConvNames[2][6][2] = {
     {{"conv/enc0a", "conv/enc0b"}, {"conv/enc1a", "conv/enc1b"}, {"conv/enc2a", "conv/enc2b"},
      {"conv/enc3a", "conv/enc3b"}, {"conv/enc4a", "conv/enc4b"}, {"conv/enc5a", "conv/enc5b"}},
@@ -819,27 +815,20 @@ static lnr_status depth_filter_impl(lnr_context *ctx, Scratch &scr, lnr_image *i
     Hs[k] = (Hs[k - 1] + 1) / 2;
     Ws[k] = (Ws[k - 1] + 1) / 2;
   }
-  // D[1..n] then U[1..n-1], each 256-byte aligned
+  // D[1..n], each 256-byte aligned
   for (int k = 1; k <= n_levels; ++k) {
     offs[k] = total;
     total += ((size_t)Hs[k] * Ws[k] * 4 + 255) / 256 * 256;
   }
-  size_t uoffs[32];
-  for (int k = 1; k < n_levels; ++k) {
-    uoffs[k] = total;
-    total += ((size_t)Hs[k] * Ws[k] * 4 + 255) / 256 * 256;
-  }
   if ((st = ensure(ctx, scr.pyramid, total)) != LNR_OK) return st;
   char *base = static_cast<char *>(scr.pyramid.p);
-  float *D[32] = {nullptr}, *U[32] = {nullptr};
+  float *D[32] = {nullptr};
   for (int k = 1; k <= n_levels; ++k) D[k] = reinterpret_cast<float *>(base + offs[k]);
-  for (int k = 1; k < n_levels; ++k) U[k] = reinterpret_cast<float *>(base + uoffs[k]);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   uint32_t *rgba = reinterpret_cast<uint32_t *>(io->rgba);
   LNR_LAUNCH(ctx, "pyramid", s, launch_pyramid(io->depth, rgba, io->height, io->width, n_levels, D, s));
-  const float one_plus_fs = 1.0f + filter_strength;
-  for (int k = n_levels - 1; k >= 0; --k)
-    LNR_LAUNCH(ctx, kUpsampleNames[k & 15], s, launch_upsample(k, n_levels, D, U, Hs, Ws, io->depth, rgba, filter_strength, one_plus_fs, s));
+  LNR_LAUNCH(ctx, "upsample", s,
+             launch_upsample_fused(n_levels, D, Hs, Ws, io->depth, rgba, filter_strength, 1.0f + filter_strength, s));
   ctx->last_stream = s;
   return LNR_OK;
 }
@@ -1235,7 +1224,7 @@ lnr_status lnr_server_create(lnr_context *ctx, const lnr_cloud *c, const lnr_une
     for (int k = 1; k <= std::max(cfg->n_levels, 1); ++k) {
       h = (h + 1) / 2;
       w = (w + 1) / 2;
-      pyr += 2 * (((size_t)h * w * 4 + 255) / 256 * 256);
+      pyr += ((size_t)h * w * 4 + 255) / 256 * 256;
     }
   }
   const size_t act = unet_layout(u, mH, mW, cfg->max_batch).bytes;

@@ -71,70 +71,127 @@ __global__ __launch_bounds__(256) void pyramid_kernel(const float *__restrict__ 
   }
 }
 
-// One thread per coarse pixel p of level k+1 handles its 2x2 children at level k.
-template <bool FINAL>
-__global__ __launch_bounds__(256) void upsample_kernel(const float *__restrict__ Dk, int Hk, int Wk,
-                                                       const float *__restrict__ Dc, const float *__restrict__ Uc,
-                                                       int Hc, int Wc, float *__restrict__ Uk,
-                                                       float *__restrict__ depth, uint32_t *__restrict__ rgba, float fs,
-                                                       float one_plus_fs) {
-  const int px = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int py = blockIdx.y * 16 + (threadIdx.x >> 4);
-  if (px >= Wc || py >= Hc) return;
+// Edge-aware upsampling of every level in one launch.  A workgroup owns a
+// kTile x kTile tile of level 0.  Level 0 needs the upsampled level 1 at the
+// tile's parents and their neighbours (3x3 reference, bilinear taps); that
+// region of level 1 needs a slightly larger region of level 2, and so on up to
+// level n (U_n = D_n).  The workgroup recomputes this chain of small regions
+// in LDS from the min-pooled levels, coarsest first, so no upsampled level is
+// written to HBM and one launch replaces one per level.  Neighbouring tiles
+// recompute the same coarse pixels with the same arithmetic, so every copy
+// holds the same value.
+constexpr int kTile = 64;
+constexpr int kReg = 36;  // side of the LDS region buffers (regions are at most 34 x 34)
+
+struct Region {
+  int r0, r1, c0, c1;  // rows [r0, r1), columns [c0, c1) of one level, inside the image
+};
+
+__device__ inline Region parent_region(const Region &c, int Hp, int Wp) {
+  // parents of c, widened by one pixel (3x3 reference and bilinear taps), clamped
+  return {max(0, (c.r0 >> 1) - 1), min(Hp, ((c.r1 - 1) >> 1) + 2), max(0, (c.c0 >> 1) - 1),
+          min(Wp, ((c.c1 - 1) >> 1) + 2)};
+}
+
+// Threshold depth of the children of coarse pixel (py, px): the Laplacian edge
+// test on the min-pooled coarse level Dc, then the reference depth from the
+// upsampled coarse level Uc (the centre, or at edges the maximum over the
+// clamped 3x3), times (1 + fs).  Dc and Uc hold region R of the coarse level.
+__device__ inline float child_threshold(const float *Dc, const float *Uc, const Region &R, int Hc, int Wc, int py,
+                                        int px, float fs, float one_plus_fs) {
   const int ym = max(py - 1, 0), yp = min(py + 1, Hc - 1);
   const int xm = max(px - 1, 0), xp = min(px + 1, Wc - 1);
-  // edge test on the min-pooled coarse level
-  const float c = Dc[(size_t)py * Wc + px];
-  const float up = Dc[(size_t)ym * Wc + px], down = Dc[(size_t)yp * Wc + px];
-  const float left = Dc[(size_t)py * Wc + xm], right = Dc[(size_t)py * Wc + xp];
-  bool edge = isinf(c) || isinf(up) || isinf(down) || isinf(left) || isinf(right);
+  const int r[3] = {ym - R.r0, py - R.r0, yp - R.r0}, c[3] = {xm - R.c0, px - R.c0, xp - R.c0};
+  const float ctr = Dc[r[1] * kReg + c[1]];
+  const float up = Dc[r[0] * kReg + c[1]], down = Dc[r[2] * kReg + c[1]];
+  const float left = Dc[r[1] * kReg + c[0]], right = Dc[r[1] * kReg + c[2]];
+  bool edge = isinf(ctr) || isinf(up) || isinf(down) || isinf(left) || isinf(right);
   if (!edge) {
-    const float lap = (((up + down) + left) + right) - 4.0f * c;
-    edge = fabsf(lap) > fs * c;
+    const float lap = (((up + down) + left) + right) - 4.0f * ctr;
+    edge = fabsf(lap) > fs * ctr;
   }
-  // upsampled coarse level, clamped 3x3 around p (clamped taps repeat in-bounds
-  // ones, so their maximum is the maximum over the in-bounds neighbourhood)
-  const int rows[3] = {ym, py, yp}, cols[3] = {xm, px, xp};
-  float u[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) u[i][j] = Uc[(size_t)rows[i] * Wc + cols[j]];
-  float ref = u[1][1];
+  // clamped taps repeat in-bounds ones, so their maximum is the maximum over
+  // the in-bounds neighbourhood
+  float ref = Uc[r[1] * kReg + c[1]];
   if (edge) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) ref = fmaxf(ref, u[i][j]);
+      for (int j = 0; j < 3; ++j) ref = fmaxf(ref, Uc[r[i] * kReg + c[j]]);
   }
-  const float thr = ref * one_plus_fs;
-#pragma unroll
-  for (int cy = 0; cy < 2; ++cy) {
-    const int y = 2 * py + cy;
-    if (y >= Hk) continue;
-#pragma unroll
-    for (int cx = 0; cx < 2; ++cx) {
-      const int x = 2 * px + cx;
-      if (x >= Wk) continue;
-      const size_t i = (size_t)y * Wk + x;
-      if (FINAL) {
-        const uint32_t q = rgba[i];
-        const float d = (q >> 24) ? depth[i] : INFINITY;
-        const bool keep = !isinf(d) && d <= thr;
-        if (!keep && (q >> 24)) {
-          depth[i] = 0.f;
-          rgba[i] = 0u;
-        }
-      } else {
-        const float d = Dk[i];
-        const bool keep = !isinf(d) && d <= thr;
-        float val = d;
-        if (!keep) {
-          const float U00 = u[1][1], U01 = u[1][cx ? 2 : 0], U10 = u[cy ? 2 : 0][1], U11 = u[cy ? 2 : 0][cx ? 2 : 0];
-          val = 0.75f * (0.75f * U00 + 0.25f * U01) + 0.25f * (0.75f * U10 + 0.25f * U11);
-        }
-        Uk[i] = val;
+  return ref * one_plus_fs;
+}
+
+struct LevelPtrs {
+  const float *D[16];  // D[k], k = 1..n: min-pooled levels
+  int H[16], W[16];    // sizes, level 0 included
+};
+
+__global__ __launch_bounds__(256) void upsample_fused_kernel(LevelPtrs lv, int n, float *__restrict__ depth,
+                                                             uint32_t *__restrict__ rgba, float fs,
+                                                             float one_plus_fs) {
+  __shared__ float sD[2][kReg * kReg], sU[2][kReg * kReg];
+  const int t = threadIdx.x;
+  Region R[16];
+  R[0] = {(int)blockIdx.y * kTile, min(lv.H[0], (int)blockIdx.y * kTile + kTile), (int)blockIdx.x * kTile,
+          min(lv.W[0], (int)blockIdx.x * kTile + kTile)};
+  for (int k = 1; k <= n; ++k) R[k] = parent_region(R[k - 1], lv.H[k], lv.W[k]);
+  // level n: U_n = D_n over R[n]
+  int cur = 0;
+  {
+    const Region &g = R[n];
+    const int rw = g.c1 - g.c0, cnt = (g.r1 - g.r0) * rw;
+    for (int i = t; i < cnt; i += 256) {
+      const int y = i / rw, x = i - y * rw;
+      const float d = lv.D[n][(size_t)(g.r0 + y) * lv.W[n] + g.c0 + x];
+      sD[0][y * kReg + x] = d;
+      sU[0][y * kReg + x] = d;
+    }
+  }
+  __syncthreads();
+  // levels n-1 .. 1: U_k over R[k] from U_{k+1} over R[k+1]
+  for (int k = n - 1; k >= 1; --k) {
+    const Region &g = R[k], &gc = R[k + 1];
+    const int rw = g.c1 - g.c0, cnt = (g.r1 - g.r0) * rw;
+    const float *Dc = sD[cur], *Uc = sU[cur];
+    float *Dn = sD[cur ^ 1], *Un = sU[cur ^ 1];
+    for (int i = t; i < cnt; i += 256) {
+      const int y = i / rw, x = i - y * rw;
+      const int gy = g.r0 + y, gx = g.c0 + x;
+      const int py = gy >> 1, px = gx >> 1;
+      const float thr = child_threshold(Dc, Uc, gc, lv.H[k + 1], lv.W[k + 1], py, px, fs, one_plus_fs);
+      const float d = lv.D[k][(size_t)gy * lv.W[k] + gx];
+      float val = d;
+      if (!(!isinf(d) && d <= thr)) {
+        // bilinear with half-pixel centres: the parent, and its neighbour on
+        // the child's side in each direction (clamped at the border)
+        const int y1 = (gy & 1) ? min(py + 1, lv.H[k + 1] - 1) : max(py - 1, 0);
+        const int x1 = (gx & 1) ? min(px + 1, lv.W[k + 1] - 1) : max(px - 1, 0);
+        const int ry0 = py - gc.r0, ry1 = y1 - gc.r0, rx0 = px - gc.c0, rx1 = x1 - gc.c0;
+        const float U00 = Uc[ry0 * kReg + rx0], U01 = Uc[ry0 * kReg + rx1];
+        const float U10 = Uc[ry1 * kReg + rx0], U11 = Uc[ry1 * kReg + rx1];
+        val = 0.75f * (0.75f * U00 + 0.25f * U01) + 0.25f * (0.75f * U10 + 0.25f * U11);
       }
+      Dn[y * kReg + x] = d;
+      Un[y * kReg + x] = val;
+    }
+    cur ^= 1;
+    __syncthreads();
+  }
+  // level 0: keep or remove each pixel of the tile
+  const Region &g = R[0], &gc = R[1];
+  const int rw = g.c1 - g.c0, cnt = (g.r1 - g.r0) * rw;
+  for (int i = t; i < cnt; i += 256) {
+    const int y = i / rw, x = i - y * rw;
+    const int gy = g.r0 + y, gx = g.c0 + x;
+    const size_t p = (size_t)gy * lv.W[0] + gx;
+    const uint32_t q = rgba[p];
+    if (!(q >> 24)) continue;  // empty pixels stay empty
+    const float d = depth[p];
+    const float thr = child_threshold(sD[cur], sU[cur], gc, lv.H[1], lv.W[1], gy >> 1, gx >> 1, fs, one_plus_fs);
+    if (!(!isinf(d) && d <= thr)) {
+      depth[p] = 0.f;
+      rgba[p] = 0u;
     }
   }
 }
@@ -167,18 +224,17 @@ hipError_t launch_pyramid(const float *depth, const uint32_t *rgba, int H, int W
   return hipSuccess;
 }
 
-hipError_t launch_upsample(int k, int n, const float *const *D, float *const *U, const int *Hs, const int *Ws,
-                           float *depth, uint32_t *rgba, float fs, float one_plus_fs, hipStream_t s) {
-  // coarse level k+1: D[k+1] min-pooled, U[k+1] upsampled (U[n] == D[n])
-  const int Hc = Hs[k + 1], Wc = Ws[k + 1];
-  dim3 grid((Wc + 15) / 16, (Hc + 15) / 16);
-  const float *Uc = (k + 1 == n) ? D[n] : U[k + 1];
-  if (k == 0)
-    upsample_kernel<true><<<grid, 256, 0, s>>>(nullptr, Hs[0], Ws[0], D[1], Uc, Hc, Wc, nullptr, depth, rgba, fs,
-                                               one_plus_fs);
-  else
-    upsample_kernel<false><<<grid, 256, 0, s>>>(D[k], Hs[k], Ws[k], D[k + 1], Uc, Hc, Wc, U[k], nullptr, nullptr, fs,
-                                                one_plus_fs);
+hipError_t launch_upsample_fused(int n, const float *const *D, const int *Hs, const int *Ws, float *depth,
+                                 uint32_t *rgba, float fs, float one_plus_fs, hipStream_t s) {
+  if (n < 1 || n > 15) return hipErrorInvalidValue;
+  LevelPtrs lv{};
+  for (int k = 0; k <= n; ++k) {
+    lv.D[k] = k ? D[k] : nullptr;
+    lv.H[k] = Hs[k];
+    lv.W[k] = Ws[k];
+  }
+  dim3 grid((Ws[0] + kTile - 1) / kTile, (Hs[0] + kTile - 1) / kTile);
+  upsample_fused_kernel<<<grid, 256, 0, s>>>(lv, n, depth, rgba, fs, one_plus_fs);
   return hipGetLastError();
 }
 

@@ -110,8 +110,10 @@ hipError_t launch_soft(const CloudDev &c, const uint2 *chunks, const uint32_t *c
 // filter.hip
 hipError_t launch_pyramid(const float *depth, const uint32_t *rgba, int H, int W, int n, float *const *levels,
                           hipStream_t s);
-hipError_t launch_upsample(int k, int n, const float *const *D, float *const *U, const int *Hs, const int *Ws,
-                           float *depth, uint32_t *rgba, float fs, float one_plus_fs, hipStream_t s);
+// every upsampling level in one launch (1 <= n <= 15); D[1..n] min-pooled levels,
+// Hs/Ws[0..n] level sizes; removes the rejected pixels of depth/rgba in place
+hipError_t launch_upsample_fused(int n, const float *const *D, const int *Hs, const int *Ws, float *depth,
+                                 uint32_t *rgba, float fs, float one_plus_fs, hipStream_t s);
 
 // unet.hip
 // values equal the public lnr_precision ones
