@@ -198,6 +198,22 @@ lnr_status lnr_measure_atomic_min(lnr_context *ctx, uint64_t n_slots, int32_t pa
  * not NaN (+inf keeps everything). */
 lnr_status lnr_depth_filter(lnr_context *ctx, lnr_image *inout, int32_t n_levels, float filter_strength,
                             void *hip_stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * filter, arguments, checks and result as lnr_depth_filter, without any device
+ * allocation.  The min-pooled levels 1..n (each padded to 256 bytes) go to a
+ * fixed 16 MiB array in device memory that the library holds, one per device,
+ * until the process ends; every image up to 3840 x 2160 fits at every
+ * n_levels, and a larger image whose levels do not fit is refused with
+ * LNR_E_INVALID_ARG before anything is enqueued.  Calls on one device share
+ * that array: calls that overlap on the device (different streams or contexts
+ * of one device) race and give undefined results; calls ordered on one stream
+ * are safe.  Nothing in the array has to start at any value (each call writes
+ * every level before reading it).  Not timed by lnr_profile_enable.
+ * LNR_E_DEVICE if the array's address could not be found when ctx was
+ * created. */
+lnr_status lnr_depth_filter_noalloc(lnr_context *ctx, lnr_image *inout, int32_t n_levels, float filter_strength,
+                                    void *hip_stream);
 
 /* Load U-Net weights (Fig. 1; Method, "U-Net Reconstruction") from a HOST
  * blob (layout: magic "LNRU", u32 version 1|2, u32 levels L, in_channels (5),

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -60,6 +61,10 @@ struct lnr_context {
   bool closed = false;
   // lnr_debug_fail_allocation: device allocations left before one fails (-1: none)
   int64_t fail_alloc_after = -1;
+  // device address of this device's allocation-free filter scratch (null if
+  // the lookup failed; noalloc_error then says why)
+  float *noalloc_scratch = nullptr;
+  std::string noalloc_error;
 };
 
 struct lnr_cloud {
@@ -453,6 +458,26 @@ lnr_status lnr_context_create(int hip_device, uint64_t hbm_budget_bytes, lnr_con
   }
   ctx->device = hip_device;
   ctx->budget = hbm_budget_bytes;
+  // the allocation-free filter's scratch: look its address up once per
+  // device, with that device current, and keep it
+  {
+    static std::mutex mu;
+    static std::map<int, std::pair<float *, hipError_t>> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(hip_device);
+    if (it == addr.end()) {
+      float *ptr = nullptr;
+      hipError_t ge = noalloc_scratch_address(&ptr);
+      if (ge != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+      }
+      it = addr.emplace(hip_device, std::make_pair(ptr, ge)).first;
+    }
+    ctx->noalloc_scratch = it->second.first;
+    if (it->second.second != hipSuccess)
+      ctx->noalloc_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(it->second.second);
+  }
   *out = ctx;
   return LNR_OK;
 }
@@ -782,8 +807,10 @@ lnr_status lnr_measure_atomic_min(lnr_context *ctx, uint64_t n_slots, int32_t pa
 // ---------------------------------------------------------------------------
 // depth filter
 // ---------------------------------------------------------------------------
+// fixed: the allocation-free entry point's per-device array (nullptr: the
+// context's grow-only scratch)
 static lnr_status depth_filter_impl(lnr_context *ctx, Scratch &scr, lnr_image *io, int32_t n_levels,
-                                    float filter_strength, void *hip_stream);
+                                    float filter_strength, void *hip_stream, float *fixed = nullptr);
 
 lnr_status lnr_depth_filter(lnr_context *ctx, lnr_image *io, int32_t n_levels, float filter_strength,
                             void *hip_stream) {
@@ -791,8 +818,16 @@ lnr_status lnr_depth_filter(lnr_context *ctx, lnr_image *io, int32_t n_levels, f
   return depth_filter_impl(ctx, ctx->sc, io, n_levels, filter_strength, hip_stream);
 }
 
+lnr_status lnr_depth_filter_noalloc(lnr_context *ctx, lnr_image *io, int32_t n_levels, float filter_strength,
+                                    void *hip_stream) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!ctx->noalloc_scratch)
+    return fail(ctx, LNR_E_DEVICE, "allocation-free scratch unavailable: " + ctx->noalloc_error);
+  return depth_filter_impl(ctx, ctx->sc, io, n_levels, filter_strength, hip_stream, ctx->noalloc_scratch);
+}
+
 static lnr_status depth_filter_impl(lnr_context *ctx, Scratch &scr, lnr_image *io, int32_t n_levels,
-                                    float filter_strength, void *hip_stream) {
+                                    float filter_strength, void *hip_stream, float *fixed) {
   if (!ctx) return LNR_E_INVALID_ARG;
   if (!io || !io->depth || !io->rgba) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
   if (io->width < 1 || io->height < 1 || io->width > 16384 || io->height > 16384)
@@ -820,15 +855,34 @@ static lnr_status depth_filter_impl(lnr_context *ctx, Scratch &scr, lnr_image *i
     offs[k] = total;
     total += ((size_t)Hs[k] * Ws[k] * 4 + 255) / 256 * 256;
   }
-  if ((st = ensure(ctx, scr.pyramid, total)) != LNR_OK) return st;
-  char *base = static_cast<char *>(scr.pyramid.p);
+  char *base;
+  if (fixed) {
+    if (total > kNoAllocScratchFloats * sizeof(float))
+      return fail(ctx, LNR_E_INVALID_ARG,
+                  "the min-pooled levels need " + std::to_string(total) + " bytes, more than the " +
+                      std::to_string(kNoAllocScratchFloats * sizeof(float)) +
+                      " bytes of the allocation-free filter's scratch");
+    base = reinterpret_cast<char *>(fixed);
+  } else {
+    if ((st = ensure(ctx, scr.pyramid, total)) != LNR_OK) return st;
+    base = static_cast<char *>(scr.pyramid.p);
+  }
   float *D[32] = {nullptr};
   for (int k = 1; k <= n_levels; ++k) D[k] = reinterpret_cast<float *>(base + offs[k]);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   uint32_t *rgba = reinterpret_cast<uint32_t *>(io->rgba);
-  LNR_LAUNCH(ctx, "pyramid", s, launch_pyramid(io->depth, rgba, io->height, io->width, n_levels, D, s));
-  LNR_LAUNCH(ctx, "upsample", s,
-             launch_upsample_fused(n_levels, D, Hs, Ws, io->depth, rgba, filter_strength, 1.0f + filter_strength, s));
+  if (fixed) {
+    // no timing events either: nothing is created or allocated on this path
+    (void)hipGetLastError();
+    LNR_HIP(ctx, launch_pyramid(io->depth, rgba, io->height, io->width, n_levels, D, s));
+    LNR_HIP(ctx, launch_upsample_fused(n_levels, D, Hs, Ws, io->depth, rgba, filter_strength,
+                                       1.0f + filter_strength, s));
+  } else {
+    LNR_LAUNCH(ctx, "pyramid", s, launch_pyramid(io->depth, rgba, io->height, io->width, n_levels, D, s));
+    LNR_LAUNCH(ctx, "upsample", s,
+               launch_upsample_fused(n_levels, D, Hs, Ws, io->depth, rgba, filter_strength, 1.0f + filter_strength,
+                                     s));
+  }
   ctx->last_stream = s;
   return LNR_OK;
 }

@@ -238,4 +238,17 @@ hipError_t launch_upsample_fused(int n, const float *const *D, const int *Hs, co
   return hipGetLastError();
 }
 
+// Scratch of the allocation-free filter entry point: the min-pooled levels
+// D_1..D_n of one image, each level starting on a 256-byte boundary.  The
+// array exists once per device for the lifetime of the process.  Host code
+// must not pass `scratch` itself to a kernel (on the host it names a stand-in,
+// not device memory): it takes the device address from
+// noalloc_scratch_address() once per device and uses that.
+static __device__ __align__(256) float scratch[kNoAllocScratchFloats];
+
+hipError_t noalloc_scratch_address(float **ptr) {
+  *ptr = nullptr;
+  return hipGetSymbolAddress(reinterpret_cast<void **>(ptr), HIP_SYMBOL(scratch));
+}
+
 }  // namespace lnr

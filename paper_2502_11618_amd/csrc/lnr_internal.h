@@ -110,6 +110,10 @@ hipError_t launch_soft(const CloudDev &c, const uint2 *chunks, const uint32_t *c
 // filter.hip
 hipError_t launch_pyramid(const float *depth, const uint32_t *rgba, int H, int W, int n, float *const *levels,
                           hipStream_t s);
+// allocation-free filter: floats in the per-device scratch array (16 MiB), and
+// its device address on the current device
+constexpr size_t kNoAllocScratchFloats = size_t(4) << 20;
+hipError_t noalloc_scratch_address(float **ptr);
 // every upsampling level in one launch (1 <= n <= 15); D[1..n] min-pooled levels,
 // Hs/Ws[0..n] level sizes; removes the rejected pixels of depth/rgba in place
 hipError_t launch_upsample_fused(int n, const float *const *D, const int *Hs, const int *Ws, float *depth,

@@ -114,6 +114,7 @@ def _load():
         "lnr_measure_atomic_min": (i32, [vp, u64, i32, u64, vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(u64)]),
         "lnr_depth_filter": (i32, [vp, ctypes.POINTER(lnr_image), i32, f32, vp]),
+        "lnr_depth_filter_noalloc": (i32, [vp, ctypes.POINTER(lnr_image), i32, f32, vp]),
         "lnr_unet_load": (i32, [vp, vp, u64, ctypes.c_int, ctypes.POINTER(vp)]),
         "lnr_unet_destroy": (None, [vp]),
         "lnr_reconstruct": (i32, [vp, vp, ctypes.POINTER(lnr_image), vp, vp]),
@@ -341,6 +342,12 @@ def lnr_depth_filter(ctx: Context, image: Image, n_levels: int, filter_strength:
     img = image.struct()
     _check(_lib.lnr_depth_filter(ctx.handle, ctypes.byref(img), int(n_levels), float(filter_strength),
                                  _stream(stream)), ctx.handle)
+
+
+def lnr_depth_filter_noalloc(ctx: Context, image: Image, n_levels: int, filter_strength: float, stream=None) -> None:
+    img = image.struct()
+    _check(_lib.lnr_depth_filter_noalloc(ctx.handle, ctypes.byref(img), int(n_levels), float(filter_strength),
+                                         _stream(stream)), ctx.handle)
 
 
 def lnr_unet_load(ctx: Context, blob: bytes, precision: int = LNR_FP32) -> UNet:
