@@ -52,14 +52,19 @@ def conv_shapes(widths, H, W, cin0):
     return out
 
 
+RENDER_KERNELS = ("clear", "cull", "bin", "tilescan", "segsort", "tile", "tileres", "splat", "resolve")
+FILTER_KERNELS = ("pyramid", "upsample")
+
+
 def algorithmic_bytes(H, W, n_levels, n_proc, n_filled, n_removed):
-    """Bytes each geometric kernel must move (reads + writes), per launch:
-    clear 8 B per pixel (the key); splat 12 B per processed point (xyz);
-    resolve 8 B per pixel read (key) + 8 B written (depth, rgba) + 4 B per
-    filled pixel (its colour); pyramid 8 B per pixel read (depth, rgba) + 4 B
-    per pixel of every coarser level written; the fused upsample 8 B per pixel
-    read + 4 B per pixel of every coarser level read + 8 B per removed pixel
-    written."""
+    """Bytes the geometric stages must move (reads + writes) per frame: the
+    projection reads 12 B per processed point (xyz) and writes 16 B per pixel
+    (key, depth, rgba) plus a 4 B colour read per filled pixel; the pyramid
+    reads 8 B per pixel (depth, rgba) and writes 4 B per pixel of every
+    coarser level; the fused upsample reads 8 B per pixel and 4 B per pixel of
+    every coarser level and writes 8 B per removed pixel.  Intermediate
+    buffers an implementation adds (z-buffer clears, binned records) are not
+    algorithmic."""
     P = H * W
     sizes = [(H, W)]
     for _ in range(n_levels):
@@ -68,11 +73,10 @@ def algorithmic_bytes(H, W, n_levels, n_proc, n_filled, n_removed):
     px = [h * w for h, w in sizes]
     coarse = 4 * sum(px[1:])
     return {
-        "clear": 8 * P,
-        "splat": 12 * n_proc,
-        "resolve": 8 * P + 8 * P + 4 * n_filled,
+        "render": 12 * n_proc + 16 * P + 4 * n_filled,
         "pyramid": 8 * P + coarse,
         "upsample": 8 * P + coarse + 8 * n_removed,
+        "bin": 12 * n_proc,
     }
 
 
@@ -711,6 +715,16 @@ def main():
     for i in range(args.steps):
         L.lnr_render(ctx, cloud, cams[i % len(cams)], img, L.LNR_RENDER_COUNT_ATOMICS)
         n_atomics.append(L.lnr_render_atomic_count(ctx))
+    # the same frames projected with the atomic splat (for comparison), per kernel
+    L.lnr_profile_enable(ctx, True)
+    L.lnr_profile_read(ctx)
+    per_kernel = {}
+    for i in range(args.steps):
+        L.lnr_render(ctx, cloud, cams[i % len(cams)], img, L.LNR_RENDER_ATOMIC_SPLAT)
+        for name, ms in L.lnr_profile_read(ctx):
+            per_kernel.setdefault(name, []).append(ms)
+    L.lnr_profile_enable(ctx, False)
+    atomic_ks = {k: (float(np.mean(v)), len(v)) for k, v in per_kernel.items()}
     atomic_rate, atomic_ops = L.lnr_measure_atomic_min(ctx, H * W, 0, 1 << 26)
     atomic_rate_contended, _ = L.lnr_measure_atomic_min(ctx, H * W, 1, 1 << 26)
 
@@ -749,23 +763,29 @@ def main():
     unet_flops = sum(flops.values()) + head_flops
     n_proc = results[p0].get("processed_points_per_frame", proc0)
     gbytes = algorithmic_bytes(H, W, NL, n_proc, filled0, filled0 - kept0)
-    geo_names = [k for k in ks if k in gbytes]
-    geo_ms = sum(ks[k][0] for k in geo_names)
-    geo_bytes = sum(gbytes[k] for k in geo_names)
-    geo_gbs = geo_bytes / (geo_ms * 1e-3) / 1e9
+
+    def geo_roofline(kstats, names, nbytes):
+        ms = sum(kstats[k][0] for k in names if k in kstats)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_frame": nbytes, "ms_per_frame": round(ms, 4),
+                "kernels": [k for k in names if k in kstats]}
+
+    rf_bytes = gbytes["render"] + gbytes["pyramid"] + gbytes["upsample"]
     rooflines = {
-        "render_and_filter": {"bound": "hbm", "achieved": round(geo_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                              "frac": round(geo_gbs / PEAK_HBM_GBS, 4), "bytes_per_frame": geo_bytes,
-                              "ms_per_frame": round(geo_ms, 4), "kernels": geo_names},
+        "render_and_filter": geo_roofline(ks, RENDER_KERNELS + FILTER_KERNELS, rf_bytes),
+        "render": geo_roofline(ks, RENDER_KERNELS, gbytes["render"]),
+        "filter": geo_roofline(ks, FILTER_KERNELS, gbytes["pyramid"] + gbytes["upsample"]),
+        "render_atomic_splat": geo_roofline(atomic_ks, RENDER_KERNELS, gbytes["render"]),
     }
-    for k in ("splat", "bin", "tile"):
-        if k in ks and k in gbytes:
+    for k in ("bin", "pyramid", "upsample"):
+        if k in ks:
             gbs = gbytes[k] / (ks[k][0] * 1e-3) / 1e9
             rooflines[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                             "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": gbytes[k],
                             "avg_launch_ms": round(ks[k][0], 4)}
-    if "splat" in ks and n_atomics:
-        rate = float(np.mean(n_atomics)) / (ks["splat"][0] * 1e-3)
+    if "splat" in atomic_ks and n_atomics:
+        rate = float(np.mean(n_atomics)) / (atomic_ks["splat"][0] * 1e-3)
         rooflines["splat_atomics"] = {
             "bound": "atomic", "achieved": round(rate, 1), "peak": round(atomic_rate, 1), "unit": "atomics/s",
             "frac": round(rate / atomic_rate, 4), "atomics_per_frame": round(float(np.mean(n_atomics)), 1),

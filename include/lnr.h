@@ -91,10 +91,21 @@ typedef struct {
  * Every precision computes the same network; only the rounding differs. */
 typedef enum { LNR_FP32 = 0, LNR_BF16 = 1, LNR_FP8_E4M3 = 2, LNR_BF16X3 = 3, LNR_FP16 = 4 } lnr_precision;
 
-/* lnr_render flag: visit every non-empty cell (no frustum test).  The result
- * is identical; this exists to check that culling is a pure speed-up. */
+/* lnr_render flags.  The image is the same under every combination.
+ *   LNR_RENDER_NO_CULL       visit every non-empty cell (no frustum test), to
+ *                            check that culling is a pure speed-up.
+ *   LNR_RENDER_ATOMIC_SPLAT  keep the z-buffer in device memory and lower it
+ *                            with 64-bit atomicMin (after a per-work-item
+ *                            on-chip z-buffer keeps the nearest point of each
+ *                            pixel), instead of the default screen-tiled
+ *                            splat (points binned per 32 x 32 tile, each
+ *                            tile's z-buffer on chip, no atomic per point or
+ *                            pixel in device memory); for comparison.
+ *   LNR_RENDER_COUNT_ATOMICS the atomic splat, also counting the z-buffer
+ *                            atomics it issues (lnr_render_atomic_count). */
 #define LNR_RENDER_NO_CULL 1u
 #define LNR_RENDER_COUNT_ATOMICS 2u
+#define LNR_RENDER_ATOMIC_SPLAT 4u
 
 /* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the
  * device memory the context, and the clouds and networks loaded through it,
@@ -144,9 +155,9 @@ void lnr_cloud_destroy(lnr_cloud *c);
  * point in it can pass the per-point test (float64 bound with slack), so
  * culling never changes the image.  out->key, depth and rgba must all be
  * non-NULL with out->width/height equal to the camera's.  flags: 0 or any of
- * LNR_RENDER_NO_CULL, LNR_RENDER_COUNT_ATOMICS (also count the z-buffer
- * atomicMin operations the projection issues, for lnr_render_atomic_count;
- * the image is the same, the projection somewhat slower: for measurement). */
+ * LNR_RENDER_NO_CULL, LNR_RENDER_ATOMIC_SPLAT, LNR_RENDER_COUNT_ATOMICS (see
+ * above; the image is the same).  The tiled splat takes 28 bytes of context
+ * scratch per point of the cloud. */
 lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out, uint32_t flags,
                       void *hip_stream);
 /* Render with the soft z-buffer of Method, "Point Cloud Projection" (colours of
@@ -167,9 +178,10 @@ lnr_status lnr_render_stats(lnr_context *ctx, uint64_t *visible_cells, uint64_t 
                             uint8_t *cull_flags_host);
 /* Number of z-buffer atomicMin operations issued by the last render on ctx,
  * which must have been issued with LNR_RENDER_COUNT_ATOMICS (else
- * LNR_E_INVALID_ARG); waits for ctx's last stream.  A point issues one when
- * its key is below the pixel's key as last read (Method, "Point Cloud
- * Projection": the z-buffer keeps the nearest point). */
+ * LNR_E_INVALID_ARG); waits for ctx's last stream.  One is issued when a key
+ * (a point's, or with the on-chip z-buffer the nearest of a work item's
+ * points on that pixel) is below the pixel's key as last read (Method, "Point
+ * Cloud Projection": the z-buffer keeps the nearest point). */
 lnr_status lnr_render_atomic_count(lnr_context *ctx, uint64_t *atomics);
 /* Roofline denominator of the projection step: the device's throughput of
  * 64-bit atomicMin, the z-buffer's operation.  Allocates n_slots u64 words

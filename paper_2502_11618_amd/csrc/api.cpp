@@ -32,6 +32,7 @@ thread_local std::string g_create_error;
 // device scratch reused by consecutive calls on one stream
 struct Scratch {
   Buf flags, chunks, counters, pyramid, act, soft_acc;
+  Buf recs, segs, sorted, tile_nseg, tile_off, tile_units, units;  // tiled splat
 };
 
 }  // namespace
@@ -486,7 +487,9 @@ namespace {
 void context_free(lnr_context *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  for (Buf *b : {&ctx->sc.flags, &ctx->sc.chunks, &ctx->sc.counters, &ctx->sc.pyramid, &ctx->sc.act, &ctx->sc.soft_acc})
+  for (Buf *b : {&ctx->sc.flags, &ctx->sc.chunks, &ctx->sc.counters, &ctx->sc.pyramid, &ctx->sc.act, &ctx->sc.soft_acc,
+                 &ctx->sc.recs, &ctx->sc.segs, &ctx->sc.sorted, &ctx->sc.tile_nseg, &ctx->sc.tile_off,
+                 &ctx->sc.tile_units, &ctx->sc.units})
     dfree(ctx, b->p, b->cap);
   for (auto &r : ctx->recs) {
     (void)hipEventDestroy(r.a);
@@ -669,13 +672,33 @@ void lnr_cloud_destroy(lnr_cloud *c) {
 // ---------------------------------------------------------------------------
 // render
 // ---------------------------------------------------------------------------
+// scratch of the tiled splat for a cloud of n_points points and grid g (see TiledSplatGrid)
+static lnr_status ensure_tiled(lnr_context *ctx, Scratch &scr, const TiledSplatGrid &g, uint32_t n_points) {
+  const size_t n = std::max<uint32_t>(1, n_points);
+  lnr_status st;
+  if ((st = ensure(ctx, scr.recs, 8 * n)) != LNR_OK || (st = ensure(ctx, scr.segs, 16 * n)) != LNR_OK ||
+      (st = ensure(ctx, scr.sorted, 4 * n)) != LNR_OK || (st = ensure(ctx, scr.tile_nseg, 4ull * g.n_tiles)) != LNR_OK ||
+      (st = ensure(ctx, scr.tile_off, 4ull * g.n_tiles + 4)) != LNR_OK ||
+      (st = ensure(ctx, scr.tile_units, 4ull * g.n_tiles)) != LNR_OK ||
+      (st = ensure(ctx, scr.units, 8ull * g.unit_cap)) != LNR_OK)
+    return st;
+  return LNR_OK;
+}
+
+static TiledSplatBufs tiled_bufs(Scratch &scr) {
+  return TiledSplatBufs{static_cast<uint64_t *>(scr.recs.p),       static_cast<uint4 *>(scr.segs.p),
+                        static_cast<uint32_t *>(scr.sorted.p),     static_cast<uint32_t *>(scr.tile_nseg.p),
+                        static_cast<uint32_t *>(scr.tile_off.p),   static_cast<uint32_t *>(scr.tile_units.p),
+                        static_cast<uint2 *>(scr.units.p)};
+}
+
 static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c, const lnr_camera *cam,
                               lnr_image *out, uint32_t flags, bool soft, float soft_eps, void *hip_stream) {
   if (!ctx) return LNR_E_INVALID_ARG;
   if (soft && !(std::isfinite(soft_eps) && soft_eps >= 0.f))
     return fail(ctx, LNR_E_INVALID_ARG, "soft_eps must be finite and >= 0");
   if (!c || !cam || !out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
-  if (flags & ~(LNR_RENDER_NO_CULL | LNR_RENDER_COUNT_ATOMICS))
+  if (flags & ~(LNR_RENDER_NO_CULL | LNR_RENDER_COUNT_ATOMICS | LNR_RENDER_ATOMIC_SPLAT))
     return fail(ctx, LNR_E_INVALID_ARG, "unknown render flags");
   std::string why;
   if (!camera_ok(cam, &why)) return fail(ctx, LNR_E_INVALID_ARG, why);
@@ -702,23 +725,32 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   sc.z_near = cam->z_near;
   sc.z_far = cam->z_far;
   sc.W = (uint32_t)cam->width;
+  const bool count = (flags & LNR_RENDER_COUNT_ATOMICS) != 0;
+  const bool atomic = count || (flags & LNR_RENDER_ATOMIC_SPLAT) != 0;
+  const TiledSplatGrid tg = tiled_splat_grid((uint32_t)cam->width, (uint32_t)cam->height, c->d.n);
   // every allocation comes before the first launch: a failure leaves the image untouched
+  if (!atomic && (st = ensure_tiled(ctx, scr, tg, c->d.n)) != LNR_OK) return st;
   if (soft && (st = ensure(ctx, scr.soft_acc, 16ull * npix)) != LNR_OK) return st;
-  LNR_LAUNCH(ctx, "clear", s, launch_clear(out->key, npix, counters, s));
+  const TiledSplatBufs tb = tiled_bufs(scr);
+  LNR_LAUNCH(ctx, "clear", s, launch_clear(out->key, npix, counters, tb.tile_nseg, atomic ? 0u : tg.n_tiles, s));
   LNR_LAUNCH(ctx, "cull", s, launch_cull(c->d, prm, static_cast<uint8_t *>(scr.flags.p), static_cast<uint2 *>(scr.chunks.p),
                            counters, s));
-  const bool count = (flags & LNR_RENDER_COUNT_ATOMICS) != 0;
-  LNR_LAUNCH(ctx, "splat", s,
-             launch_splat(c->d, static_cast<const uint2 *>(scr.chunks.p), counters, sc, out->key, count, s));
-  if (soft) {
-    LNR_LAUNCH(ctx, "soft", s,
-               launch_soft(c->d, static_cast<const uint2 *>(scr.chunks.p), counters, sc, out->key, 1.0f + soft_eps,
-                           static_cast<uint32_t *>(scr.soft_acc.p), out->depth, reinterpret_cast<uint32_t *>(out->rgba),
-                           npix, s));
+  const uint2 *chunks = static_cast<const uint2 *>(scr.chunks.p);
+  uint32_t *rgba32 = reinterpret_cast<uint32_t *>(out->rgba);
+  if (atomic) {
+    LNR_LAUNCH(ctx, "splat", s, launch_splat(c->d, chunks, counters, sc, out->key, count, s));
+    if (!soft) LNR_LAUNCH(ctx, "resolve", s, launch_resolve(out->key, c->d.rgbx, out->depth, rgba32, npix, s));
   } else {
-    LNR_LAUNCH(ctx, "resolve", s,
-               launch_resolve(out->key, c->d.rgbx, out->depth, reinterpret_cast<uint32_t *>(out->rgba), npix, s));
+    static const char *const names[5] = {"bin", "tilescan", "segsort", "tile", "tileres"};
+    for (int stage = 0; stage < 5; ++stage)
+      LNR_LAUNCH(ctx, names[stage], s,
+                 launch_tiled_splat(c->d, chunks, counters, sc, (uint32_t)cam->height, tb, out->key, out->depth,
+                                    rgba32, stage, s));
   }
+  if (soft)
+    LNR_LAUNCH(ctx, "soft", s,
+               launch_soft(c->d, chunks, counters, sc, out->key, 1.0f + soft_eps,
+                           static_cast<uint32_t *>(scr.soft_acc.p), out->depth, rgba32, npix, s));
   ctx->last_stream = s;
   ctx->rendered = true;
   ctx->counted = count;
@@ -1202,7 +1234,8 @@ void server_release(lnr_server *srv) {
     if (l.stream) (void)hipStreamSynchronize(l.stream);
     for (auto &g : l.graphs) (void)hipGraphExecDestroy(g.second);
     for (auto g : l.graph_defs) (void)hipGraphDestroy(g);
-    for (Buf *b : {&l.sc.flags, &l.sc.chunks, &l.sc.counters, &l.sc.pyramid, &l.sc.act, &l.sc.soft_acc})
+    for (Buf *b : {&l.sc.flags, &l.sc.chunks, &l.sc.counters, &l.sc.pyramid, &l.sc.act, &l.sc.soft_acc, &l.sc.recs,
+                   &l.sc.segs, &l.sc.sorted, &l.sc.tile_nseg, &l.sc.tile_off, &l.sc.tile_units, &l.sc.units})
       dfree(ctx, b->p, b->cap);
     if (l.head_outs_dev) dfree(ctx, l.head_outs_dev, 8ull * 16);
     if (l.head_outs_host) (void)hipHostFree(l.head_outs_host);
@@ -1295,6 +1328,7 @@ lnr_status lnr_server_create(lnr_context *ctx, const lnr_cloud *c, const lnr_une
         (st = ensure(ctx, l.sc.chunks, 8ull * kDepthBuckets * std::max<uint32_t>(1, c->d.max_chunks))) != LNR_OK ||
         (st = ensure(ctx, l.sc.counters, 4 * kCounterWords)) != LNR_OK || (st = ensure(ctx, l.sc.pyramid, pyr)) != LNR_OK ||
         (st = ensure(ctx, l.sc.act, act)) != LNR_OK ||
+        (st = ensure_tiled(ctx, l.sc, tiled_splat_grid((uint32_t)mW, (uint32_t)mH, c->d.n), c->d.n)) != LNR_OK ||
         (cfg->soft && (st = ensure(ctx, l.sc.soft_acc, 16 * npix)) != LNR_OK) ||
         (st = dalloc(ctx, (void **)&l.head_outs_dev, 8ull * 16)) != LNR_OK) {
       server_release(srv.get());

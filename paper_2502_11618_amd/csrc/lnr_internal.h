@@ -61,7 +61,10 @@ struct SplatCam {
 // [2..3] processed points (u64), [4 + b] chunks queued in depth bucket b,
 // [kAtomicWord] z-buffer atomics issued (counting renders only)
 constexpr int kAtomicWord = 4 + kDepthBuckets;
-constexpr int kCounterWords = kAtomicWord + 1;
+// tiled splat: segments written so far, and units of work of its tile kernel
+constexpr int kSegTopWord = kAtomicWord + 1;
+constexpr int kUnitsWord = kSegTopWord + 1;
+constexpr int kCounterWords = kUnitsWord + 1;
 
 // ----------------------------------------------------------------------------
 // kernel launchers (each returns hipGetLastError() of its launches)
@@ -88,10 +91,37 @@ hipError_t launch_cell_aabb(const float *x, const float *y, const float *z, cons
 hipError_t launch_chunk_count(const uint32_t *cell_start, uint32_t n_cells, uint32_t *total, hipStream_t s);
 
 // render.hip
-hipError_t launch_clear(uint64_t *key, uint32_t npix, uint32_t *counters, hipStream_t s);
+// per-frame reset of the key buffer (npix words), the counters and the tiled
+// splat's per-tile segment counts (n_tiles words)
+hipError_t launch_clear(uint64_t *key, uint32_t npix, uint32_t *counters, uint32_t *tile_nseg, uint32_t n_tiles,
+                        hipStream_t s);
+// Screen-tiled splat (32 x 32 pixel tiles), in five launches (stage 0..4:
+// bin, tilescan, segsort, tile, tileres).  Scratch per render for a cloud of
+// n points: recs u64[n] (a work item's records at its points' positions),
+// segs uint4[n] and sorted u32[n] (at most one segment per record),
+// tile_nseg, tile_units u32[n_tiles], tile_off u32[n_tiles + 1], units
+// uint2[unit_cap].
+struct TiledSplatGrid {
+  uint32_t tiles_x = 0, tiles_y = 0, n_tiles = 0;
+  uint64_t unit_cap = 0;
+};
+TiledSplatGrid tiled_splat_grid(uint32_t W, uint32_t H, uint32_t n_points);
+struct TiledSplatBufs {
+  uint64_t *recs;
+  uint4 *segs;
+  uint32_t *sorted;
+  uint32_t *tile_nseg;
+  uint32_t *tile_off;
+  uint32_t *tile_units;
+  uint2 *units;
+};
+hipError_t launch_tiled_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counters, const SplatCam &cam,
+                              uint32_t H, const TiledSplatBufs &b, uint64_t *key, float *depth, uint32_t *rgba,
+                              int stage, hipStream_t s);
 hipError_t launch_cull(const CloudDev &c, const CullParams &prm, uint8_t *flags, uint2 *chunks, uint32_t *counters,
                        hipStream_t s);
-// count_atomics: also add the number of z-buffer atomics issued to counters[kAtomicWord]
+// the atomic splat (global z-buffer); count_atomics: also add the number of
+// z-buffer atomics issued to counters[kAtomicWord]
 hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counters, const SplatCam &cam,
                         uint64_t *key, bool count_atomics, hipStream_t s);
 // throughput probe: grid x 256 threads x iters 64-bit atomicMin on buf[n_slots]

@@ -12,6 +12,8 @@
 // which is order independent, so the image does not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lnr_internal.h"
 
 #pragma clang fp contract(off)
@@ -21,10 +23,14 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Per-frame reset: the key buffer (npix words), the render counters and the
+// tiled splat's per-tile segment counts (n_tiles words, may be 0).
 __global__ __launch_bounds__(kThreads) void clear_kernel(uint64_t *__restrict__ key, uint32_t npix,
-                                                         uint32_t *__restrict__ counters) {
+                                                         uint32_t *__restrict__ counters,
+                                                         uint32_t *__restrict__ tile_nseg, uint32_t n_tiles) {
   const uint32_t stride = gridDim.x * kThreads;
   for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < npix; i += stride) key[i] = ~0ull;
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n_tiles; i += stride) tile_nseg[i] = 0u;
   if (blockIdx.x == 0 && threadIdx.x < kCounterWords) counters[threadIdx.x] = 0;
 }
 
@@ -125,41 +131,496 @@ __device__ inline bool work_item(uint32_t i, const uint32_t *__restrict__ counte
 
 // One block per work item.  Keys only ever decrease, so a (possibly stale)
 // relaxed read of the pixel's key is an upper bound of its current value and
-// the atomic can be skipped when the new key is not smaller.  COUNT adds the
-// number of atomics issued to counters[kAtomicWord] (one add per wave), for
-// measurement; the keys written are the same.
+// the atomic can be skipped when the new key is not smaller.
+//
+// When the work item's points fall in a screen rectangle of at most
+// kDedupPx pixels, they first meet in an LDS z-buffer over that rectangle
+// (LDS 64-bit atomicMin), and only the nearest point of each pixel goes on to
+// the global z-buffer, in row order: dense surfaces (many points per pixel)
+// then cost one coalesced early-out read, and at most one atomic, per pixel
+// instead of per point.  A work item spread over a larger rectangle (a near
+// surface, few points per pixel) takes the per-point path.  The minimum is the
+// same either way.
+//
+// COUNT adds the number of global atomics issued to counters[kAtomicWord]
+// (one add per wave), for measurement; the keys written are the same.
+constexpr int kDedupPx = 4096;
+constexpr int kPtsPerThread = kSplatChunk / kThreads;
+static_assert(kSplatChunk % kThreads == 0, "work items must split evenly over the threads");
+
+template <bool COUNT>
+__device__ inline void global_min(uint64_t *dst, uint64_t k, uint32_t &issued) {
+  // relaxed atomic read: other blocks lower the word concurrently
+  if (k < __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    atomicMin(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)k);
+    if constexpr (COUNT) ++issued;
+  }
+}
+
+// Project the work item's points (thread t takes points t, t + 256, ...):
+// kk = key, (px, py) = pixel, px = ~0u if the point is not drawn; and the
+// screen rectangle [x0, x1] x [y0, y1] of the drawn points over the whole
+// block (x0 > x1 if none).  Contains block barriers.
+__device__ inline void project_work_item(const float *__restrict__ xs, const float *__restrict__ ys,
+                                         const float *__restrict__ zs, uint2 ch, const SplatCam &cam,
+                                         uint64_t (&kk)[kPtsPerThread], uint32_t (&px)[kPtsPerThread],
+                                         uint32_t (&py)[kPtsPerThread], uint32_t *s_bb, uint32_t *rx0, uint32_t *ry0,
+                                         uint32_t *rx1, uint32_t *ry1) {
+  const int tid = threadIdx.x;
+  const float *P = cam.P;
+  uint32_t x0 = ~0u, y0 = ~0u, x1 = 0, y1 = 0;
+#pragma unroll
+  for (int q = 0; q < kPtsPerThread; ++q) {
+    const uint32_t i = tid + q * kThreads;
+    px[q] = ~0u;
+    py[q] = 0;
+    kk[q] = 0;
+    if (i < ch.y) {
+      const uint32_t j = ch.x + i;
+      const float x = xs[j], y = ys[j], z = zs[j];
+      const float a = ((P[0] * x + P[1] * y) + P[2] * z) + P[3];
+      const float b = ((P[4] * x + P[5] * y) + P[6] * z) + P[7];
+      const float w = ((P[8] * x + P[9] * y) + P[10] * z) + P[11];
+      if (w >= cam.z_near && w <= cam.z_far) {
+        const float u = a / w;
+        const float v = b / w;
+        if (u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf) {
+          px[q] = (uint32_t)u;
+          py[q] = (uint32_t)v;
+          kk[q] = ((uint64_t)__float_as_uint(w) << 32) | j;
+          x0 = min(x0, px[q]);
+          x1 = max(x1, px[q]);
+          y0 = min(y0, py[q]);
+          y1 = max(y1, py[q]);
+        }
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    x0 = min(x0, (uint32_t)__shfl_xor(x0, off, 64));
+    y0 = min(y0, (uint32_t)__shfl_xor(y0, off, 64));
+    x1 = max(x1, (uint32_t)__shfl_xor(x1, off, 64));
+    y1 = max(y1, (uint32_t)__shfl_xor(y1, off, 64));
+  }
+  if (tid == 0) {
+    s_bb[0] = ~0u;
+    s_bb[1] = ~0u;
+    s_bb[2] = 0;
+    s_bb[3] = 0;
+  }
+  __syncthreads();
+  if ((tid & 63) == 0) {
+    atomicMin(&s_bb[0], x0);
+    atomicMin(&s_bb[1], y0);
+    atomicMax(&s_bb[2], x1);
+    atomicMax(&s_bb[3], y1);
+  }
+  __syncthreads();
+  *rx0 = s_bb[0];
+  *ry0 = s_bb[1];
+  *rx1 = s_bb[2];
+  *ry1 = s_bb[3];
+}
+
 template <bool COUNT>
 __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
                                                          const float *__restrict__ zs, const uint2 *__restrict__ chunks,
                                                          uint32_t cap, uint32_t *__restrict__ counters,
                                                          SplatCam cam, uint64_t *__restrict__ key) {
+  __shared__ unsigned long long zb[kDedupPx];
+  __shared__ uint32_t s_bb[4];
   uint2 ch;
   if (!work_item(blockIdx.x, counters, chunks, cap, &ch)) return;
+  const int tid = threadIdx.x;
   uint32_t issued = 0;
-  const float *P = cam.P;
-  // (keeping several points per thread in flight was measured slower: the
-  // kernel is bound by the z-buffer atomics, not by load latency)
-  for (uint32_t i = threadIdx.x; i < ch.y; i += kThreads) {
-    const uint32_t j = ch.x + i;
-    const float x = xs[j], y = ys[j], z = zs[j];
-    const float a = ((P[0] * x + P[1] * y) + P[2] * z) + P[3];
-    const float b = ((P[4] * x + P[5] * y) + P[6] * z) + P[7];
-    const float w = ((P[8] * x + P[9] * y) + P[10] * z) + P[11];
-    if (!(w >= cam.z_near && w <= cam.z_far)) continue;
-    const float u = a / w;
-    const float v = b / w;
-    if (!(u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf)) continue;
-    const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | j;
-    uint64_t *dst = key + (size_t)(uint32_t)v * cam.W + (uint32_t)u;
-    // relaxed atomic read: other lanes lower the word concurrently
-    if (k < __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-      atomicMin(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)k);
-      if constexpr (COUNT) ++issued;
+  uint64_t kk[kPtsPerThread];
+  uint32_t px[kPtsPerThread], py[kPtsPerThread];
+  uint32_t x0, y0, x1, y1;
+  project_work_item(xs, ys, zs, ch, cam, kk, px, py, s_bb, &x0, &y0, &x1, &y1);
+  if (x0 > x1) return;  // nothing drawn (the same for the whole block)
+  const uint32_t bw = x1 - x0 + 1;
+  const uint64_t a64 = (uint64_t)bw * (uint64_t)(y1 - y0 + 1);
+  if (a64 <= (uint64_t)kDedupPx) {
+    const uint32_t area = (uint32_t)a64;
+    for (uint32_t p = tid; p < area; p += kThreads) zb[p] = ~0ull;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPtsPerThread; ++q)
+      if (px[q] != ~0u) atomicMin(&zb[(py[q] - y0) * bw + (px[q] - x0)], (unsigned long long)kk[q]);
+    __syncthreads();
+    for (uint32_t p = tid; p < area; p += kThreads) {
+      const uint64_t k = zb[p];
+      if (k == ~0ull) continue;
+      const uint32_t ry = p / bw, rx = p - ry * bw;
+      global_min<COUNT>(key + (size_t)(y0 + ry) * cam.W + (x0 + rx), k, issued);
     }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kPtsPerThread; ++q)
+      if (px[q] != ~0u) global_min<COUNT>(key + (size_t)py[q] * cam.W + px[q], kk[q], issued);
   }
   if constexpr (COUNT) {
     for (int off = 32; off > 0; off >>= 1) issued += __shfl_xor(issued, off, 64);
-    if ((threadIdx.x & 63) == 0 && issued) atomicAdd(&counters[kAtomicWord], issued);
+    if ((tid & 63) == 0 && issued) atomicAdd(&counters[kAtomicWord], issued);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Screen-tiled splat (the default): no global atomic per point or pixel.
+//
+//   bin       one workgroup per work item: project the points; if they fall
+//             in a screen rectangle of at most kDedupPx pixels, keep only the
+//             nearest of each pixel (LDS z-buffer); counting-sort the rest by
+//             32 x 32 screen tile in LDS and write them, grouped by tile, as
+//             8-byte records at the work item's own place in the record
+//             array.  Each (work item, tile) group is a segment.
+//   tilescan  one workgroup: per-tile segment offsets, and the units of work
+//             of the tile kernel: up to kSegsPerUnit segments of one tile.
+//   segsort   groups the segment ids by tile.
+//   tile      one workgroup per unit: LDS z-buffer of the tile over the
+//             unit's records.  A tile of one unit owns its pixels and writes
+//             key, depth and rgba (the resolve) with plain stores; the units
+//             of a busier tile merge their minima into the key buffer with
+//             atomicMin (one per pixel and unit), and
+//   tileres   resolves those tiles afterwards.
+//
+// A record is (float32 depth bits << 32) | (pixel within the tile << 12) |
+// (point index - work item start); the tile kernel rebuilds the key
+// (depth bits << 32) | sorted index, so the image equals the atomic splat's.
+// ---------------------------------------------------------------------------
+constexpr int kTileShift = 5;  // 32 x 32 pixel tiles
+constexpr int kTileSide = 1 << kTileShift;
+constexpr int kTilePx = kTileSide * kTileSide;
+constexpr int kHistBins = 1024;  // tiles one binning pass can address
+constexpr int kSegsPerUnit = 32;
+static_assert(kSplatChunk <= 4096, "a record keeps 12 bits of point offset");
+
+// exclusive prefix over the block (blockDim.x = NT): each thread passes its
+// value and gets the sum of the values of lower threads; *total receives the
+// sum over the block
+template <int NT>
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp /* [NT / 64] */, uint32_t *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) s_tmp[wave] = incl;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const uint32_t x = s_tmp[w];
+    if (w < wave) wbase += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return wbase + incl - v;
+}
+
+struct TileGrid {
+  uint32_t tiles_x, tiles_y, n_tiles;
+};
+
+__global__ __launch_bounds__(kThreads) void bin_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
+                                                       const float *__restrict__ zs, const uint2 *__restrict__ chunks,
+                                                       uint32_t cap, uint32_t *__restrict__ counters, SplatCam cam,
+                                                       TileGrid tg, uint64_t *__restrict__ recs,
+                                                       uint4 *__restrict__ segs, uint32_t *__restrict__ tile_nseg) {
+  // The work item's entries live in LDS, one u64 per slot (~0 = none).  With
+  // the on-chip z-buffer, slot = pixel of the rectangle (row order) and the
+  // entry its nearest key (depth bits << 32 | point index); otherwise slot =
+  // point (index - work item start) and the entry (depth bits << 32 |
+  // py << 16 | px).
+  __shared__ unsigned long long s_ent[kDedupPx];
+  __shared__ uint32_t s_hist[kHistBins];
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  __shared__ uint32_t s_bb[4];
+  __shared__ uint32_t s_seg_base;
+  uint2 ch;
+  if (!work_item(blockIdx.x, counters, chunks, cap, &ch)) return;
+  const int tid = threadIdx.x;
+  uint32_t x0, y0, x1, y1, bw, nslots;
+  bool dedup;
+  {
+    uint64_t kk[kPtsPerThread];
+    uint32_t px[kPtsPerThread], py[kPtsPerThread];
+    project_work_item(xs, ys, zs, ch, cam, kk, px, py, s_bb, &x0, &y0, &x1, &y1);
+    if (x0 > x1) return;  // nothing drawn (the same for the whole block)
+    bw = x1 - x0 + 1;
+    const uint64_t a64 = (uint64_t)bw * (uint64_t)(y1 - y0 + 1);
+    dedup = a64 <= (uint64_t)kDedupPx;
+    if (dedup) {
+      nslots = (uint32_t)a64;
+      for (uint32_t p = tid; p < nslots; p += kThreads) s_ent[p] = ~0ull;
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kPtsPerThread; ++q)
+        if (px[q] != ~0u) atomicMin(&s_ent[(py[q] - y0) * bw + (px[q] - x0)], (unsigned long long)kk[q]);
+    } else {
+      nslots = ch.y;
+#pragma unroll
+      for (int q = 0; q < kPtsPerThread; ++q) {
+        const uint32_t i = tid + q * kThreads;
+        if (i < ch.y)
+          s_ent[i] = px[q] == ~0u ? ~0ull : ((kk[q] & 0xFFFFFFFF00000000ull) | (py[q] << 16) | px[q]);
+      }
+    }
+  }
+  __syncthreads();
+  // pixel and key of an entry in slot p
+  auto decode = [&](uint32_t p, uint64_t e, uint32_t *gx, uint32_t *gy) -> uint64_t {
+    if (dedup) {
+      const uint32_t ry = p / bw;
+      *gy = y0 + ry;
+      *gx = x0 + (p - ry * bw);
+      return e;
+    }
+    *gy = ((uint32_t)e >> 16) & 0xFFFFu;
+    *gx = (uint32_t)e & 0xFFFFu;
+    return (e & 0xFFFFFFFF00000000ull) | (uint64_t)(ch.x + p);
+  };
+  // counting sort of the entries by tile, in rounds of tile rows so that one
+  // round addresses at most kHistBins tiles
+  const uint32_t tx0 = x0 >> kTileShift, ty0 = y0 >> kTileShift;
+  const uint32_t tbw = (x1 >> kTileShift) - tx0 + 1, ty1 = y1 >> kTileShift;
+  const uint32_t rows_per_round = max(1u, (uint32_t)kHistBins / tbw);
+  uint32_t rec_next = 0;  // records written by earlier rounds
+  for (uint32_t r0 = ty0; r0 <= ty1; r0 += rows_per_round) {
+    const uint32_t r1 = min(ty1 + 1, r0 + rows_per_round);
+    const uint32_t tbins = (r1 - r0) * tbw;
+    // a row wider than the histogram is split into column ranges
+    for (uint32_t c0 = 0; c0 < tbins; c0 += kHistBins) {
+      const uint32_t nbins = min((uint32_t)kHistBins, tbins - c0);
+      for (uint32_t b = tid; b < nbins; b += kThreads) s_hist[b] = 0;
+      __syncthreads();
+      for (uint32_t p = tid; p < nslots; p += kThreads) {
+        const uint64_t e = s_ent[p];
+        if (e == ~0ull) continue;
+        uint32_t gx, gy;
+        decode(p, e, &gx, &gy);
+        const uint32_t ty = gy >> kTileShift;
+        const uint32_t bin = (ty - r0) * tbw + ((gx >> kTileShift) - tx0) - c0;
+        if (ty >= r0 && ty < r1 && bin < nbins) atomicAdd(&s_hist[bin], 1u);
+      }
+      __syncthreads();
+      // exclusive prefix over the bins of record counts and non-empty flags
+      // at once (16-bit halves: at most 4096 of each); a thread owns kPer bins
+      constexpr int kPer = kHistBins / kThreads;
+      uint32_t sum = 0;
+      for (int q = 0; q < kPer; ++q) {
+        const uint32_t b = tid * kPer + q;
+        const uint32_t c = b < nbins ? s_hist[b] : 0u;
+        sum += (c << 16) | (c ? 1u : 0u);
+      }
+      uint32_t total;
+      uint32_t run = block_exclusive_scan<kThreads>(sum, s_tmp, &total);
+      const uint32_t n_rec = total >> 16, n_seg = total & 0xFFFFu;
+      if (n_rec == 0) continue;  // uniform: nothing in these bins
+      if (tid == 0) s_seg_base = atomicAdd(&counters[kSegTopWord], n_seg);
+      __syncthreads();
+      const uint32_t seg_base = s_seg_base;
+      for (int q = 0; q < kPer; ++q) {
+        const uint32_t b = tid * kPer + q;
+        if (b >= nbins) break;
+        const uint32_t c = s_hist[b];
+        const uint32_t first = rec_next + (run >> 16);
+        if (c) {
+          const uint32_t tb = c0 + b;
+          const uint32_t tile = (r0 + tb / tbw) * tg.tiles_x + (tx0 + tb % tbw);
+          segs[seg_base + (run & 0xFFFFu)] = make_uint4(tile, ch.x + first, c, ch.x);
+          atomicAdd(&tile_nseg[tile], 1u);
+        }
+        s_hist[b] = first;  // bin -> cursor at its first record
+        run += (c << 16) | (c ? 1u : 0u);
+      }
+      __syncthreads();
+      for (uint32_t p = tid; p < nslots; p += kThreads) {
+        const uint64_t e = s_ent[p];
+        if (e == ~0ull) continue;
+        uint32_t gx, gy;
+        const uint64_t k = decode(p, e, &gx, &gy);
+        const uint32_t ty = gy >> kTileShift;
+        const uint32_t bin = (ty - r0) * tbw + ((gx >> kTileShift) - tx0) - c0;
+        if (ty < r0 || ty >= r1 || bin >= nbins) continue;
+        const uint32_t pos = atomicAdd(&s_hist[bin], 1u);
+        const uint32_t local = ((gy & (kTileSide - 1)) << kTileShift) | (gx & (kTileSide - 1));
+        recs[ch.x + pos] = (k & 0xFFFFFFFF00000000ull) | ((uint64_t)local << 12) | (uint64_t)((uint32_t)k - ch.x);
+      }
+      rec_next += n_rec;
+      __syncthreads();
+    }
+  }
+}
+
+// One workgroup: per-tile segment offsets (tile_off[n_tiles + 1]) and the
+// units of the tile kernel: a tile with s segments gets max(1, ceil(s /
+// kSegsPerUnit)) units (tile_units[t]); units[u] = (tile, first segment of
+// the unit within the tile); counters[kUnitsWord] = number of units.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void tilescan_kernel(const uint32_t *__restrict__ tile_nseg, TileGrid tg,
+                                                                uint32_t *__restrict__ tile_off,
+                                                                uint32_t *__restrict__ tile_units,
+                                                                uint2 *__restrict__ units, uint32_t unit_cap,
+                                                                uint32_t *__restrict__ counters) {
+  __shared__ uint32_t s_tmp[kScanThreads / 64];
+  const int tid = threadIdx.x;
+  uint32_t seg_base = 0, unit_base = 0;
+  for (uint32_t t0 = 0; t0 < tg.n_tiles; t0 += kScanThreads) {
+    const uint32_t t = t0 + tid;
+    const uint32_t ns = t < tg.n_tiles ? tile_nseg[t] : 0u;
+    const uint32_t nu = t < tg.n_tiles ? max(1u, (ns + kSegsPerUnit - 1) / kSegsPerUnit) : 0u;
+    uint32_t tot_s, tot_u;
+    const uint32_t es = block_exclusive_scan<kScanThreads>(ns, s_tmp, &tot_s);
+    const uint32_t eu = block_exclusive_scan<kScanThreads>(nu, s_tmp, &tot_u);
+    if (t < tg.n_tiles) {
+      tile_off[t] = seg_base + es;
+      tile_units[t] = nu;
+      for (uint32_t k = 0; k < nu; ++k)
+        if (unit_base + eu + k < unit_cap) units[unit_base + eu + k] = make_uint2(t, k * kSegsPerUnit);
+    }
+    seg_base += tot_s;
+    unit_base += tot_u;
+  }
+  if (tid == 0) {
+    tile_off[tg.n_tiles] = seg_base;
+    counters[kUnitsWord] = min(unit_base, unit_cap);
+  }
+}
+
+// Segment ids grouped by tile: segment i of tile t goes to one of the places
+// [tile_off[t], tile_off[t + 1]) (their order is irrelevant: the tile kernel
+// takes a minimum).  Counts tile_nseg back down to zero.
+__global__ __launch_bounds__(kThreads) void segsort_kernel(const uint4 *__restrict__ segs,
+                                                           const uint32_t *__restrict__ counters,
+                                                           const uint32_t *__restrict__ tile_off,
+                                                           uint32_t *__restrict__ tile_nseg,
+                                                           uint32_t *__restrict__ sorted) {
+  const uint32_t n = counters[kSegTopWord];
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+    const uint32_t t = segs[i].x;
+    sorted[tile_off[t] + atomicSub(&tile_nseg[t], 1u) - 1u] = i;
+  }
+}
+
+__device__ inline void resolve_px(uint64_t k, const uint32_t *__restrict__ rgbx, size_t i, float *__restrict__ depth,
+                                  uint32_t *__restrict__ rgba) {
+  if (k == ~0ull) {
+    depth[i] = 0.f;
+    rgba[i] = 0u;
+  } else {
+    depth[i] = __uint_as_float((uint32_t)(k >> 32));
+    rgba[i] = (rgbx[(uint32_t)k] & 0x00FFFFFFu) | (1u << 24);
+  }
+}
+
+// Units of work, grid-stride: the LDS z-buffer of one tile over the records
+// of up to kSegsPerUnit of its segments.
+__global__ __launch_bounds__(kThreads) void tile_kernel(const uint64_t *__restrict__ recs,
+                                                        const uint4 *__restrict__ segs,
+                                                        const uint32_t *__restrict__ sorted,
+                                                        const uint32_t *__restrict__ tile_off,
+                                                        const uint32_t *__restrict__ tile_units,
+                                                        const uint2 *__restrict__ units,
+                                                        const uint32_t *__restrict__ counters, TileGrid tg,
+                                                        const uint32_t *__restrict__ rgbx, uint32_t W, uint32_t H,
+                                                        uint64_t *__restrict__ key, float *__restrict__ depth,
+                                                        uint32_t *__restrict__ rgba) {
+  __shared__ unsigned long long zb[kTilePx];
+  __shared__ uint32_t s_pref[kSegsPerUnit + 1];
+  __shared__ uint2 s_seg[kSegsPerUnit];  // first record, work item start
+  const int tid = threadIdx.x;
+  const uint32_t n_units = counters[kUnitsWord];
+  for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+    const uint2 un = units[u];
+    const uint32_t t = un.x;
+    const uint32_t beg = tile_off[t] + un.y, end = min(tile_off[t + 1], beg + kSegsPerUnit);
+    const uint32_t nb = end > beg ? end - beg : 0u;
+    for (int p = tid; p < kTilePx; p += kThreads) zb[p] = ~0ull;
+    if (tid < 64) {  // the unit's segments and the prefix of their record counts (one wave)
+      uint32_t c = 0;
+      if ((uint32_t)tid < nb) {
+        const uint4 sg = segs[sorted[beg + tid]];
+        s_seg[tid] = make_uint2(sg.y, sg.w);
+        c = sg.z;
+      }
+      uint32_t incl = c;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off, 64);
+        if (tid >= off) incl += o;
+      }
+      if (tid <= kSegsPerUnit) s_pref[tid] = incl - c;  // s_pref[nb] = total
+    }
+    __syncthreads();
+    const uint32_t total = s_pref[nb];
+    // kInFlight records per thread: their loads are issued before the first
+    // LDS atomic, so their latencies overlap
+    constexpr int kInFlight = 4;
+    for (uint32_t r0 = tid; r0 < total; r0 += kInFlight * kThreads) {
+      uint64_t rc[kInFlight];
+      uint32_t base[kInFlight];
+#pragma unroll
+      for (int m = 0; m < kInFlight; ++m) {
+        const uint32_t r = r0 + m * kThreads;
+        rc[m] = ~0ull;
+        base[m] = 0;
+        if (r < total) {
+          uint32_t lo = 0, hi = nb;  // the last segment whose prefix is <= r
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_pref[mid] <= r) lo = mid;
+            else hi = mid;
+          }
+          const uint2 sg = s_seg[lo];
+          rc[m] = recs[sg.x + (r - s_pref[lo])];
+          base[m] = sg.y;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kInFlight; ++m) {
+        if (rc[m] == ~0ull) continue;
+        const uint64_t k = (rc[m] & 0xFFFFFFFF00000000ull) | (uint64_t)(base[m] + (uint32_t)(rc[m] & 0xFFFu));
+        atomicMin(&zb[(rc[m] >> 12) & (kTilePx - 1)], (unsigned long long)k);
+      }
+    }
+    __syncthreads();
+    const bool alone = tile_units[t] == 1;
+    const uint32_t tx = t % tg.tiles_x, ty = t / tg.tiles_x;
+    for (int p = tid; p < kTilePx; p += kThreads) {
+      const uint32_t gx = (tx << kTileShift) + (p & (kTileSide - 1));
+      const uint32_t gy = (ty << kTileShift) + (p >> kTileShift);
+      if (gx >= W || gy >= H) continue;
+      const size_t i = (size_t)gy * W + gx;
+      const uint64_t k = zb[p];
+      if (alone) {
+        key[i] = k;
+        resolve_px(k, rgbx, i, depth, rgba);
+      } else if (k != ~0ull) {
+        atomicMin(reinterpret_cast<unsigned long long *>(key + i), (unsigned long long)k);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Resolve of the tiles whose units merged through the key buffer.
+__global__ __launch_bounds__(kThreads) void tileres_kernel(const uint32_t *__restrict__ tile_units, TileGrid tg,
+                                                           const uint32_t *__restrict__ rgbx, uint32_t W, uint32_t H,
+                                                           const uint64_t *__restrict__ key, float *__restrict__ depth,
+                                                           uint32_t *__restrict__ rgba) {
+  const uint32_t t = blockIdx.x;
+  if (tile_units[t] == 1) return;
+  const uint32_t tx = t % tg.tiles_x, ty = t / tg.tiles_x;
+  for (int p = threadIdx.x; p < kTilePx; p += kThreads) {
+    const uint32_t gx = (tx << kTileShift) + (p & (kTileSide - 1));
+    const uint32_t gy = (ty << kTileShift) + (p >> kTileShift);
+    if (gx >= W || gy >= H) continue;
+    const size_t i = (size_t)gy * W + gx;
+    resolve_px(key[i], rgbx, i, depth, rgba);
   }
 }
 
@@ -275,8 +736,54 @@ inline uint32_t grid_for(uint32_t n) {
 
 }  // namespace
 
-hipError_t launch_clear(uint64_t *key, uint32_t npix, uint32_t *counters, hipStream_t s) {
-  clear_kernel<<<grid_for(npix), kThreads, 0, s>>>(key, npix, counters);
+hipError_t launch_clear(uint64_t *key, uint32_t npix, uint32_t *counters, uint32_t *tile_nseg, uint32_t n_tiles,
+                        hipStream_t s) {
+  clear_kernel<<<grid_for(npix > n_tiles ? npix : n_tiles), kThreads, 0, s>>>(key, npix, counters, tile_nseg,
+                                                                             n_tiles);
+  return hipGetLastError();
+}
+
+TiledSplatGrid tiled_splat_grid(uint32_t W, uint32_t H, uint32_t n_points) {
+  TiledSplatGrid g;
+  g.tiles_x = (W + kTileSide - 1) >> kTileShift;
+  g.tiles_y = (H + kTileSide - 1) >> kTileShift;
+  g.n_tiles = g.tiles_x * g.tiles_y;
+  // a tile has max(1, ceil(s / kSegsPerUnit)) units, and there are at most
+  // n_points segments (one record at least each)
+  g.unit_cap = 2ull * g.n_tiles + n_points / kSegsPerUnit + 1;
+  return g;
+}
+
+hipError_t launch_tiled_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counters, const SplatCam &cam,
+                              uint32_t H, const TiledSplatBufs &b, uint64_t *key, float *depth, uint32_t *rgba,
+                              int stage, hipStream_t s) {
+  if (c.max_chunks == 0) return hipErrorInvalidValue;  // a loaded cloud has at least one point
+  const TiledSplatGrid g = tiled_splat_grid(cam.W, H, c.n);
+  const TileGrid tg{g.tiles_x, g.tiles_y, g.n_tiles};
+  switch (stage) {
+    case 0:
+      bin_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, c.max_chunks, counters, cam, tg, b.recs,
+                                                  b.segs, b.tile_nseg);
+      break;
+    case 1:
+      tilescan_kernel<<<1, kScanThreads, 0, s>>>(b.tile_nseg, tg, b.tile_off, b.tile_units, b.units,
+                                                 (uint32_t)g.unit_cap, counters);
+      break;
+    case 2:
+      segsort_kernel<<<1024, kThreads, 0, s>>>(b.segs, counters, b.tile_off, b.tile_nseg, b.sorted);
+      break;
+    case 3: {
+      const uint64_t grid = std::min<uint64_t>(g.unit_cap, std::max<uint64_t>(2ull * g.n_tiles, 4096));
+      tile_kernel<<<(uint32_t)grid, kThreads, 0, s>>>(b.recs, b.segs, b.sorted, b.tile_off, b.tile_units, b.units,
+                                                      counters, tg, c.rgbx, cam.W, H, key, depth, rgba);
+      break;
+    }
+    case 4:
+      tileres_kernel<<<g.n_tiles, kThreads, 0, s>>>(b.tile_units, tg, c.rgbx, cam.W, H, key, depth, rgba);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -290,10 +797,11 @@ hipError_t launch_cull(const CloudDev &c, const CullParams &prm, uint8_t *flags,
 hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counters, const SplatCam &cam,
                         uint64_t *key, bool count_atomics, hipStream_t s) {
   if (c.max_chunks == 0) return hipSuccess;
+  const uint32_t g = c.max_chunks, cap = c.max_chunks;
   if (count_atomics)
-    splat_kernel<true><<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, c.max_chunks, counters, cam, key);
+    splat_kernel<true><<<g, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, cap, counters, cam, key);
   else
-    splat_kernel<false><<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, c.max_chunks, counters, cam, key);
+    splat_kernel<false><<<g, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, cap, counters, cam, key);
   return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ LNR_FP16 = 4
 
 LNR_RENDER_NO_CULL = 1
 LNR_RENDER_COUNT_ATOMICS = 2
+LNR_RENDER_ATOMIC_SPLAT = 4
 
 EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
 

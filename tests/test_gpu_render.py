@@ -209,6 +209,97 @@ def test_counting_render_is_bit_exact_and_counts_plausibly(lnr, ctx, room_cloud,
     assert e.value.status == lnr.LNR_E_INVALID_ARG
 
 
+def test_tiled_splat_equals_atomic_splat(lnr, ctx, room_cloud, room_grid, room_cams):
+    """The default screen-tiled splat (points binned per 32 x 32 tile, each
+    tile's z-buffer on chip) and the atomic one (global z-buffer lowered with
+    atomicMin) give the same key, depth and rgba: on the room frames and on
+    grazing cameras with odd image sizes (partial tiles at the borders)."""
+    rng = np.random.default_rng(5)
+    cams = list(room_cams[:8])
+    while len(cams) < 20:
+        j, k = rng.integers(0, len(room_grid.xs), 2)
+        eye = np.array([room_grid.xs[j], room_grid.ys[j], room_grid.zs[j]], np.float64) + rng.normal(0, 0.3, 3)
+        tgt = np.array([room_grid.xs[k], room_grid.ys[k], room_grid.zs[k]], np.float64)
+        if np.linalg.norm(tgt - eye) < 0.3:
+            continue
+        cams.append(synth.look_at(eye, tgt, int(rng.integers(1, 300)), int(rng.integers(1, 300)),
+                                  float(rng.uniform(20, 160))))
+    for i, cam in enumerate(cams):
+        a = image_to_host(render_gpu(lnr, ctx, room_cloud, cam))
+        b = image_to_host(render_gpu(lnr, ctx, room_cloud, cam, flags=lnr.LNR_RENDER_ATOMIC_SPLAT))
+        assert_images_equal(a, b, f"tiled vs atomic, camera {i} ({cam.width}x{cam.height})")
+
+
+def _identity_camera(W, H):
+    """(u, v, w) = (x, y, z): the pixel of a point is (floor(x / z), floor(y / z))."""
+    return synth.Camera(P=np.float32([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]), width=W, height=H)
+
+
+def _check_both_splats(lnr, ctx, xyz, rgb, cell, cam, what):
+    g = G.partition(xyz, rgb, cell)
+    cloud = lnr.lnr_cloud_load(ctx, xyz, rgb, cell)
+    want = R.render(g, cam)
+    assert_images_equal(image_to_host(render_gpu(lnr, ctx, cloud, cam)), want, f"{what} tiled")
+    assert_images_equal(image_to_host(render_gpu(lnr, ctx, cloud, cam, flags=lnr.LNR_RENDER_ATOMIC_SPLAT)), want,
+                        f"{what} atomic")
+    return g, want
+
+
+@pytest.mark.parametrize("bw,bh", [(64, 64), (65, 64), (1, 1), (4096, 1), (1, 4097), (37, 19)])
+def test_splat_work_item_rectangle_limits(lnr, ctx, bw, bh):
+    """One work item of 4096 points whose pixels fill a bw x bh rectangle: at
+    most 4096 pixels keep only the nearest point per pixel on chip before
+    binning, larger ones bin every point.  Half the points lie at depth 1 and
+    half at depth 2 behind them, with many exact depth ties per pixel (the
+    lowest index must win)."""
+    rng = np.random.default_rng(bw * 7 + bh)
+    n = 4096
+    ux = rng.integers(0, bw, n) + 10.25
+    vy = rng.integers(0, bh, n) + 20.5
+    w = np.where(np.arange(n) % 2 == 0, 1.0, 2.0)
+    xyz = np.stack([ux * w, vy * w, w], axis=1).astype(np.float32)
+    rgb = rng.integers(0, 256, (n, 3), dtype=np.uint8)
+    g, want = _check_both_splats(lnr, ctx, xyz, rgb, 1e4, _identity_camera(bw + 20, bh + 30), f"{bw}x{bh}")
+    assert g.n_cells == 1
+    assert int((want[2].reshape(-1, 4)[:, 3] != 0).sum()) == len(set(zip(ux.tolist(), vy.tolist())))
+
+
+@pytest.mark.parametrize("W,H", [(2048, 2048), (3000, 3000), (4000, 1000)])
+def test_tiled_splat_work_item_spanning_many_tiles(lnr, ctx, W, H):
+    """One cell whose points spread over the whole of a large image: the work
+    item touches more tiles (up to 94 x 94) than one binning pass addresses
+    (4096), so it is binned in several rounds of tile rows."""
+    rng = np.random.default_rng(W + H)
+    n = 4000
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    xyz = (d * rng.uniform(1.0, 3.0, (n, 1))).astype(np.float32)
+    xyz[:50] = xyz[50:100]  # duplicates: ties go to the lowest index
+    rgb = rng.integers(0, 256, (n, 3), dtype=np.uint8)
+    cam = synth.look_at([0, 0, 0], [1, 0.1, 0.05], W, H, 170.0)
+    g, want = _check_both_splats(lnr, ctx, xyz, rgb, 10.0, cam, f"{W}x{H} single cell")
+    assert g.n_cells == 1
+    assert int((want[2].reshape(-1, 4)[:, 3] != 0).sum()) > 500
+
+
+def test_tiled_splat_busy_tiles_split_into_units(lnr, ctx):
+    """About 2,300 work items over four 32 x 32 tiles: each of those tiles has
+    far more segments than one unit of the tile kernel takes (32), so its
+    units merge through the key buffer; the rest of the image is empty
+    tiles.  Many points share a pixel, at different and at equal depths."""
+    rng = np.random.default_rng(17)
+    n = 100_000
+    u = rng.uniform(0, 64, n)
+    v = rng.uniform(0, 64, n)
+    z = rng.choice(np.float32([2.0, 2.5, 3.0]), n) + rng.integers(0, 2, n) * rng.uniform(0, 0.5, n)
+    xyz = np.stack([u * z, v * z, z], axis=1).astype(np.float32)
+    rgb = rng.integers(0, 256, (n, 3), dtype=np.uint8)
+    g, want = _check_both_splats(lnr, ctx, xyz, rgb, 4.0, _identity_camera(100, 70), "busy tiles")
+    assert g.n_cells > 1000
+    filled = want[2].reshape(70, 100, 4)[..., 3] != 0
+    assert filled[:64, :64].mean() > 0.99 and not filled[:, 64:].any()
+
+
 @pytest.mark.parametrize("pattern", [0, 1])
 def test_atomic_min_probe(lnr, ctx, pattern):
     """The throughput probe runs whole blocks of 256 x 64 operations and
