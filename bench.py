@@ -31,8 +31,8 @@ if ROOT not in sys.path:
 
 METRIC = "frames/s and p50/p99 latency at 1080p/20M pts; BF16 vs FP32 U-Net at stated PSNR"
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
-TOL = {"fp32": 1e-4, "bf16": 2e-2, "bf16x3": 2e-2, "fp16": 2e-2}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0}
+TOL = {"fp32": 1e-4, "bf16": 2e-2, "bf16x3": 2e-2, "fp16": 2e-2, "fp8": 8e-2, "fp8x3": 8e-2}
 
 
 def log(*a):
@@ -353,8 +353,8 @@ def largest_scene(args):
     """The largest configuration: 300M points from 16 scans of an 80 x 60 x 10 m
     scene of 32 rooms (2 m cells); batches of 8 consecutive orbit-path views at
     3840x2160; depth filter n = 6, fs = 0.5; U-Net widths 32/64/128/256/512 in
-    fp32, split bf16 and bf16 (bf16 in place of the e4m3 this configuration
-    names, judged by its 8e-2 bound).  A batch renders, filters and reconstructs its
+    fp32, fp16, split bf16, bf16, split e4m3 and e4m3, each judged by its own
+    bound (e4m3: 8e-2).  A batch renders, filters and reconstructs its
     8 views one after the other into 8 output images (a 4K view fills the GPU
     on its own).  Reports views/s, batch time, per-view latency, the U-Net's
     share against the matrix peak and the sampled error of view 0 against the
@@ -377,7 +377,8 @@ def largest_scene(args):
     info = L.lnr_cloud_info(cloud)
     log(f"cloud loaded and partitioned in {load_s:.2f} s, grid {info['dims']}")
     cams = synth.orbit_path(scene, 120, W, H, FOV)
-    prec_ids = {"fp32": L.LNR_FP32, "bf16x3": L.LNR_BF16X3, "bf16": L.LNR_BF16}
+    prec_ids = {"fp32": L.LNR_FP32, "fp16": L.LNR_FP16, "bf16x3": L.LNR_BF16X3, "bf16": L.LNR_BF16,
+                "fp8x3": L.LNR_FP8_E4M3X3, "fp8": L.LNR_FP8_E4M3}
     nets = {p: L.lnr_unet_load(ctx, blob, i) for p, i in prec_ids.items()}
     img = L.Image(H, W)
     outs = [torch.empty((3, H, W), dtype=torch.float32, device="cuda") for _ in range(BATCH)]
@@ -414,7 +415,7 @@ def largest_scene(args):
             e.record()
         torch.cuda.synchronize()
         unet_ms = float(np.mean([a.elapsed_time(e) for a, e in ue]))
-        peak = PEAK_TFLOPS["fp32"] if p == "fp32" else PEAK_TFLOPS["bf16"]
+        peak = PEAK_TFLOPS["fp32" if p == "fp32" else ("fp8" if p.startswith("fp8") else "bf16")]
         res[p] = {"views_per_s": round(NBATCH * BATCH / wall, 2), "ms_per_batch": round(1000 * wall / NBATCH, 3),
                   "view_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                                       "p99": round(float(np.percentile(lat, 99)), 3)},
@@ -439,8 +440,7 @@ def largest_scene(args):
         L.lnr_reconstruct(ctx, net, img, outs[0])
         torch.cuda.synchronize()
         host[p] = outs[0].cpu().numpy().astype(np.float64)
-    # this configuration names e4m3 with an 8e-2 bound; bf16 takes its place
-    err = sampled_error(fd, fr, blob, host, H, W, progress=log, tol=dict(TOL, bf16=8e-2))
+    err = sampled_error(fd, fr, blob, host, H, W, progress=log)
     for p in res:
         res[p]["error_vs_fp64_sampled"] = err[p]
     print(json.dumps({"mode": "largest", "workload": "huge-300M-pts-16-scans-8x4K-batches",
@@ -456,7 +456,8 @@ def largest_scene(args):
 def precision_tier(args):
     """The precision tier on the larger scene: 100M points from 8 scans (1 m
     cells), 60 frames of the orbit path at 1920x1080 and at 2560x1440, depth
-    filter n = 5, fs = 0.5, U-Net 32/64/128/256 in fp32, split bf16 and bf16:
+    filter n = 5, fs = 0.5, U-Net 32/64/128/256 in fp32, fp16, split bf16,
+    bf16, split e4m3 and e4m3:
     frames/s, per-frame latency and the sampled error against the float64
     oracle of each precision.  Prints one JSON line."""
     import numpy as np
@@ -474,7 +475,8 @@ def precision_tier(args):
     t0 = time.perf_counter()
     cloud = L.lnr_cloud_load(ctx, scene.xyz, scene.rgb, 1.0)
     load_s = time.perf_counter() - t0
-    prec_ids = {"fp32": L.LNR_FP32, "bf16x3": L.LNR_BF16X3, "bf16": L.LNR_BF16}
+    prec_ids = {"fp32": L.LNR_FP32, "fp16": L.LNR_FP16, "bf16x3": L.LNR_BF16X3, "bf16": L.LNR_BF16,
+                "fp8x3": L.LNR_FP8_E4M3X3, "fp8": L.LNR_FP8_E4M3}
     nets = {p: L.lnr_unet_load(ctx, blob, i) for p, i in prec_ids.items()}
     out_all = {}
     for W, H in ((1920, 1080), (2560, 1440)):
@@ -530,7 +532,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--points", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precisions", default="fp32,fp16,bf16x3,bf16")
+    ap.add_argument("--precisions", default="fp32,fp16,bf16x3,bf16,fp8x3,fp8")
     ap.add_argument("--no-error-check", action="store_true", help="skip the float64 error windows")
     ap.add_argument("--pipelined", action="store_true",
                     help="overlap the next frame's projection and filter (second stream and context) with the "
@@ -539,7 +541,7 @@ def main():
     ap.add_argument("--mode", default="frames", choices=["frames", "copy", "counters", "precision-tier", "largest"],
                     help="copy: only a plain 1 GiB device copy (calibrates HBM byte counters); "
                          "counters: summarise rocprofv3 FETCH_SIZE/WRITE_SIZE csv files (no GPU); "
-                         "precision-tier: the 100M-point scene at 1080p and 1440p in all three precisions; "
+                         "precision-tier: the 100M-point scene at 1080p and 1440p in every precision; "
                          "largest: the 300M-point scene, batches of 8 views at 3840x2160, 5-level U-Net")
     ap.add_argument("--fetch-csv", help="counters mode: FETCH_SIZE counter_collection.csv of a frames run")
     ap.add_argument("--write-csv", help="counters mode: WRITE_SIZE counter_collection.csv of a frames run")
@@ -591,7 +593,8 @@ def main():
     load_s = time.perf_counter() - t0
     info = L.lnr_cloud_info(cloud)
     log(f"cloud loaded and partitioned in {load_s:.2f} s, grid {info['dims']}")
-    prec_ids = {"fp32": L.LNR_FP32, "bf16": L.LNR_BF16, "bf16x3": L.LNR_BF16X3, "fp16": L.LNR_FP16}
+    prec_ids = {"fp32": L.LNR_FP32, "bf16": L.LNR_BF16, "bf16x3": L.LNR_BF16X3, "fp16": L.LNR_FP16,
+                "fp8": L.LNR_FP8_E4M3, "fp8x3": L.LNR_FP8_E4M3X3}
     precs = [p for p in args.precisions.split(",") if p]
     nets = {p: L.lnr_unet_load(ctx, blob, prec_ids[p]) for p in precs}
     img = L.Image(H, W)
@@ -791,14 +794,17 @@ def main():
             "frac": round(rate / atomic_rate, 4), "atomics_per_frame": round(float(np.mean(n_atomics)), 1),
             "peak_kind": f"measured: {atomic_ops} 64-bit atomicMin on pseudo-random words of a {W}x{H} buffer",
             "contended_peak": round(atomic_rate_contended, 1)}
+    def peak_kind(p):  # the matrix peak of the operand type
+        return "fp32" if p == "fp32" else ("fp8" if p.startswith("fp8") else "bf16")
+
     for p in precs:
         kp = kernel_stats[p]
         ms = sum(v[0] for k, v in kp.items() if k.startswith("conv/") or k in ("pack", "head"))
-        peak = PEAK_TFLOPS["fp32" if p == "fp32" else "bf16"]
+        peak = PEAK_TFLOPS[peak_kind(p)]
         if p == "fp32":
             ex = sum(mfma_flops.values()) + head_flops
-        elif p == "bf16x3":
-            ex = 3.0 * unet_flops  # three bf16 passes per product
+        elif p in ("bf16x3", "fp8x3"):
+            ex = 3.0 * unet_flops  # three passes per product
         else:
             ex = unet_flops
         rooflines[f"unet_{p}_all_convs"] = {
@@ -806,8 +812,8 @@ def main():
             "frac": round(ex / (ms * 1e-3) / 1e12 / peak, 4), "executed_flops_per_frame": ex,
             "effective_tflops": round(unet_flops / (ms * 1e-3) / 1e12, 2), "ms_per_frame": round(ms, 4)}
         if p != p0:
-            rooflines[f"dominant_{p}_kernel"] = conv_roofline(kp, "fp32" if p == "fp32" else "bf16",
-                                                              {k: (3.0 * v if p == "bf16x3" else v)
+            rooflines[f"dominant_{p}_kernel"] = conv_roofline(kp, peak_kind(p),
+                                                              {k: (3.0 * v if p in ("bf16x3", "fp8x3") else v)
                                                                for k, v in flops.items()})[1]
 
     fps = results[p0]["frames_per_s"]

@@ -78,9 +78,14 @@ typedef struct {
 /* U-Net arithmetic (the paper fixes none; Method, "U-Net Reconstruction").
  *   LNR_FP32     : float32 activations, float32 matrix-core products.
  *   LNR_BF16     : bfloat16 activations and weights, float32 accumulation.
- *   LNR_FP8_E4M3 : OCP e4m3 operands with per-output-channel weight scales,
- *                  float32 accumulation.  This build returns
- *                  LNR_E_UNSUPPORTED for it from lnr_unet_load.
+ *   LNR_FP8_E4M3 : OCP e4m3 matrix-core operands, float32 accumulation:
+ *                  float16 activations rounded to e4m3 (to nearest even,
+ *                  saturating at 448) as they are multiplied, e4m3 weights
+ *                  with one scale per output channel (its largest weight maps
+ *                  to 448).
+ *   LNR_FP8_E4M3X3 : as LNR_FP8_E4M3 with each operand split into e4m3 high
+ *                  + low parts (low = e4m3 of the remainder), multiplied as
+ *                  lo*hi + hi*lo + hi*hi.
  *   LNR_BF16X3   : float32 activations; each operand split into bfloat16
  *                  high + low parts and multiplied as hi*hi + hi*lo + lo*hi
  *                  with float32 accumulation (near-float32 accuracy on
@@ -89,7 +94,14 @@ typedef struct {
  *                  accumulation: the data movement and matrix rate of
  *                  LNR_BF16 with a 10- instead of a 7-bit fraction.
  * Every precision computes the same network; only the rounding differs. */
-typedef enum { LNR_FP32 = 0, LNR_BF16 = 1, LNR_FP8_E4M3 = 2, LNR_BF16X3 = 3, LNR_FP16 = 4 } lnr_precision;
+typedef enum {
+  LNR_FP32 = 0,
+  LNR_BF16 = 1,
+  LNR_FP8_E4M3 = 2,
+  LNR_BF16X3 = 3,
+  LNR_FP16 = 4,
+  LNR_FP8_E4M3X3 = 5
+} lnr_precision;
 
 /* lnr_render flags.  The image is the same under every combination.
  *   LNR_RENDER_NO_CULL       visit every non-empty cell (no frustum test), to

@@ -285,6 +285,30 @@ uint16_t host_f2h(float f) {
   return u;
 }
 
+// OCP 8-bit e4m3 (sign, 4 exponent bits with bias 7, 3 fraction bits; no
+// infinities; the largest finite value 448 = 1.75 * 2^8; subnormals m * 2^-9):
+// round to nearest, ties to even, saturating at +-448 (the device's
+// v_cvt_pk_fp8_f32 rounds the same way)
+uint8_t host_e4m3(double x) {
+  const uint8_t sgn = std::signbit(x) ? 0x80 : 0x00;
+  const double a = std::fabs(x);
+  if (!(a < 464.0)) return sgn | 0x7E;  // beyond the half-way point above 448 (and NaN) saturate
+  if (a < 0x1p-6) return sgn | (uint8_t)std::nearbyint(a * 512.0);  // 8 = the smallest normal, 0x08
+  int e = std::ilogb(a);
+  double m = std::nearbyint((std::ldexp(a, -e) - 1.0) * 8.0);
+  if (m == 8.0) {
+    m = 0.0;
+    ++e;
+  }
+  if (e + 7 > 15 || (e + 7 == 15 && m > 6.0)) return sgn | 0x7E;
+  return sgn | (uint8_t)((e + 7) << 3) | (uint8_t)m;
+}
+double host_e4m3_value(uint8_t v) {
+  const int E = (v >> 3) & 15, m = v & 7;
+  const double a = E == 0 ? m * 0x1p-9 : (1.0 + m / 8.0) * std::ldexp(1.0, E - 7);
+  return (v & 0x80) ? -a : a;
+}
+
 
 // ---------------------------------------------------------------------------
 // U-Net activation layout for a batch of B same-shape images, and its launches
@@ -927,9 +951,9 @@ lnr_status lnr_unet_load(lnr_context *ctx, const void *blob_host, uint64_t bytes
   if (!ctx) return LNR_E_INVALID_ARG;
   if (!blob_host || !out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
   *out = nullptr;
-  if (prec != LNR_FP32 && prec != LNR_BF16 && prec != LNR_BF16X3 && prec != LNR_FP16 && prec != LNR_FP8_E4M3)
+  if (prec != LNR_FP32 && prec != LNR_BF16 && prec != LNR_BF16X3 && prec != LNR_FP16 && prec != LNR_FP8_E4M3 &&
+      prec != LNR_FP8_E4M3X3)
     return fail(ctx, LNR_E_INVALID_ARG, "unknown precision");
-  if (prec == LNR_FP8_E4M3) return fail(ctx, LNR_E_UNSUPPORTED, "LNR_FP8_E4M3 is not built");
   const uint8_t *p = static_cast<const uint8_t *>(blob_host);
   size_t off = 0;
   auto rd_u32 = [&](uint32_t *v) -> bool {
@@ -1078,6 +1102,32 @@ lnr_status lnr_unet_load(lnr_context *ctx, const void *blob_host, uint64_t bytes
       std::vector<uint16_t> h(np);
       for (size_t i = 0; i < np; ++i) h[i] = host_f2h(packed[i]);
       if ((st = upload(h.data(), 2 * np, &cl.w)) != LNR_OK) return free_all(), st;
+    } else if (u->prec == Prec::FP8 || u->prec == Prec::FP8X3) {
+      // one scale per output channel: its largest weight (of the float64,
+      // batch-norm-folded weights) maps to 448; the lo plane holds the e4m3 of
+      // what rounding the scaled weight to e4m3 left
+      std::vector<uint8_t> hi(np, 0), lo(np, 0);
+      std::vector<float> scale(cl.cout_pad, 1.f);
+      const size_t row = (size_t)9 * cl.cin_pad;
+      for (int o = 0; o < (int)co; ++o) {
+        double amax = 0;
+        for (int i = 0; i < (int)ci; ++i)
+          for (int t = 0; t < 9; ++t) amax = std::max(amax, std::fabs(Wd[((size_t)o * ci + i) * 9 + t]));
+        const double sc = amax > 0 ? amax / 448.0 : 1.0;
+        scale[o] = (float)sc;
+        for (int i = 0; i < (int)ci; ++i)
+          for (int t = 0; t < 9; ++t) {
+            const size_t q = (size_t)o * row + (size_t)t * cl.cin_pad + i;
+            const double v = Wd[((size_t)o * ci + i) * 9 + t] / (double)scale[o];
+            hi[q] = host_e4m3(v);
+            lo[q] = host_e4m3(v - host_e4m3_value(hi[q]));
+          }
+      }
+      if ((st = upload(hi.data(), np, &cl.w)) != LNR_OK) return free_all(), st;
+      if (u->prec == Prec::FP8X3 && (st = upload(lo.data(), np, &cl.w_lo)) != LNR_OK) return free_all(), st;
+      void *sp;
+      if ((st = upload(scale.data(), 4 * scale.size(), &sp)) != LNR_OK) return free_all(), st;
+      cl.wscale = static_cast<float *>(sp);
     } else {
       std::vector<uint16_t> hi(np), lo(np);
       for (size_t i = 0; i < np; ++i) {

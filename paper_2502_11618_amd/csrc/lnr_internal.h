@@ -151,8 +151,9 @@ hipError_t launch_upsample_fused(int n, const float *const *D, const int *Hs, co
 
 // unet.hip
 // values equal the public lnr_precision ones
-enum class Prec { F32 = 0, BF16 = 1, FP8 = 2, BF16X3 = 3, FP16 = 4 };
-inline bool prec_half(Prec p) { return p == Prec::BF16 || p == Prec::FP16; }
+enum class Prec { F32 = 0, BF16 = 1, FP8 = 2, BF16X3 = 3, FP16 = 4, FP8X3 = 5 };
+// 16-bit activations in HBM (the e4m3 modes keep float16 activations)
+inline bool prec_half(Prec p) { return p == Prec::BF16 || p == Prec::FP16 || p == Prec::FP8 || p == Prec::FP8X3; }
 
 struct ConvLayer {
   int cout = 0, cin = 0, k = 3;  // logical sizes
@@ -162,6 +163,7 @@ struct ConvLayer {
   void *w_lo = nullptr;          // bf16 low parts (BF16X3)
   float *bias = nullptr;         // [cout_pad]
   void *wu = nullptr;            // float32 only: Winograd F(2x2,3x3) weights G g G^T [cout_pad][16][cin_pad]
+  float *wscale = nullptr;       // e4m3 modes: weight scale per output channel [cout_pad]
 };
 
 struct ConvCall {

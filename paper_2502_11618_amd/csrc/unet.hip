@@ -18,6 +18,13 @@
 //   FP16   float16 activations and weights, v_mfma_f32_32x32x16_f16, float32
 //          accumulation, round-to-nearest-even to float16 on store (the same
 //          data movement as BF16, with a 10- instead of a 7-bit fraction).
+//   FP8    float16 activations in HBM, rounded to OCP e4m3 (to nearest even,
+//          saturating at 448) as they are staged into LDS; e4m3 weights with
+//          one scale per output channel (its largest weight maps to 448);
+//          v_mfma_f32_32x32x16_fp8_fp8 with float32 accumulation; the
+//          epilogue multiplies by the channel's scale.
+//   FP8X3  as FP8, with every operand split into e4m3 hi + lo (lo = e4m3 of
+//          the remainder) and the product taken as lo*hi + hi*lo + hi*hi.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -32,6 +39,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 __device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ inline long as_i64(uint2 v) { return __builtin_bit_cast(long, v); }
 __device__ inline f16x8 as_f16x8(uint4 v) { return __builtin_bit_cast(f16x8, v); }
 
 struct ConvArgs {
@@ -56,15 +64,20 @@ struct ConvArgs {
   const float *rgbda_depth;
   const uint32_t *rgbda_rgba;
   const float *wu;  // float32 Winograd-domain weights [cout_pad][16][cin_pad], or null
+  const float *wscale;  // e4m3 modes: per-output-channel weight scale [cout_pad]
 };
 
 // 3x3 convolution as implicit GEMM (M = output channels, N = pixels, K = 9 taps
-// x input channels), one kernel for the three precisions:
+// x input channels), one kernel for every precision:
 //   MODE 0  float32 activations and weights, v_mfma_f32_32x32x2_f32;
 //   MODE 1  bf16 activations and weights, v_mfma_f32_32x32x16_bf16;
 //   MODE 2  float32 activations, each operand split into bf16 hi + lo in LDS
 //           (weights are stored split), product hi*hi + hi*lo + lo*hi;
-//   MODE 3  fp16 activations and weights, v_mfma_f32_32x32x16_f16.
+//   MODE 3  fp16 activations and weights, v_mfma_f32_32x32x16_f16;
+//   MODE 4  fp16 activations rounded to e4m3 as they are staged, e4m3 weights
+//           scaled per output channel, v_mfma_f32_32x32x16_fp8_fp8;
+//   MODE 5  as MODE 4 with hi + lo e4m3 planes of both operands (weights are
+//           stored split), product lo*hi + hi*lo + hi*hi.
 // Workgroup tile: 4R rows x 32 columns of output pixels x BM output channels;
 // wave w owns rows [wR, wR + R).  Per staged chunk of CK input channels the
 // input tile with its halo and the chunk's weights ([co][tap][CK], one copy per
@@ -90,15 +103,40 @@ __device__ inline uint32_t pack_f16x2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));  // round to nearest even
 }
 // two float32 values -> the 16-bit storage format of MODE 1 (bf16) or MODE 3 (fp16)
+// activations stored as float16 (the fp16 and both e4m3 modes) or bfloat16
+constexpr bool f16_store(int mode) { return mode == 3 || mode == 4 || mode == 5; }
 template <int MODE>
 __device__ inline uint32_t pack16x2(float lo, float hi) {
-  if constexpr (MODE == 3) return pack_f16x2(lo, hi);
+  if constexpr (f16_store(MODE)) return pack_f16x2(lo, hi);
   else return pack_bf16x2(lo, hi);
 }
 template <int MODE>
 __device__ inline float unpack16(uint32_t bits16) {
-  if constexpr (MODE == 3) return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+  if constexpr (f16_store(MODE)) return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
   else return __uint_as_float(bits16 << 16);
+}
+// eight float16 values (a 16-byte vector) -> eight OCP e4m3 bytes, rounded to
+// nearest even, saturating at +-448; with LO, the e4m3 of what the first
+// rounding left (x - e4m3(x)) instead
+template <bool LO>
+__device__ inline int f16x2_to_e4m3(uint32_t w, int old, bool high_word) {
+  float f0 = (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu));
+  float f1 = (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+  f0 = fminf(fmaxf(f0, -448.f), 448.f);
+  f1 = fminf(fmaxf(f1, -448.f), 448.f);
+  if constexpr (LO) {
+    const int h = __builtin_amdgcn_cvt_pk_fp8_f32(f0, f1, 0, false);
+    f0 = f0 - __builtin_amdgcn_cvt_f32_fp8(h, 0);
+    f1 = f1 - __builtin_amdgcn_cvt_f32_fp8(h, 1);
+  }
+  return high_word ? __builtin_amdgcn_cvt_pk_fp8_f32(f0, f1, old, true)
+                   : __builtin_amdgcn_cvt_pk_fp8_f32(f0, f1, old, false);
+}
+template <bool LO>
+__device__ inline uint2 f16x8_to_e4m3(uint4 v) {
+  const int a = f16x2_to_e4m3<LO>(v.y, f16x2_to_e4m3<LO>(v.x, 0, false), true);
+  const int b = f16x2_to_e4m3<LO>(v.w, f16x2_to_e4m3<LO>(v.z, 0, false), true);
+  return make_uint2((uint32_t)a, (uint32_t)b);
 }
 
 template <int MODE>
@@ -108,6 +146,7 @@ struct ConvTraits<0> {  // float32
   using In = float;       // activations in HBM
   using W = float;        // weights in HBM
   using L = float;        // LDS element
+  using Frag = uint4;     // one lane's operand fragment in LDS
   static constexpr int kInVec = 4, kWVec = 4;    // elements per 16-byte HBM vector
   static constexpr int kPad = 4, kPlanes = 1, kGroup = 8;
 };
@@ -116,6 +155,7 @@ struct ConvTraits<1> {  // bf16
   using In = uint16_t;
   using W = uint16_t;
   using L = uint16_t;
+  using Frag = uint4;
   static constexpr int kInVec = 8, kWVec = 8;
   static constexpr int kPad = 8, kPlanes = 1, kGroup = 16;
 };
@@ -124,16 +164,37 @@ struct ConvTraits<2> {  // float32 activations, split bf16 operands
   using In = float;
   using W = uint16_t;
   using L = uint16_t;
+  using Frag = uint4;
   static constexpr int kInVec = 4, kWVec = 8;
   static constexpr int kPad = 8, kPlanes = 2, kGroup = 16;
 };
 template <>
 struct ConvTraits<3> : ConvTraits<1> {};  // fp16: bf16's data movement
+template <>
+struct ConvTraits<4> {  // float16 activations in HBM, e4m3 bytes in LDS
+  using In = uint16_t;
+  using W = uint8_t;
+  using L = uint8_t;
+  using Frag = uint2;  // 8 e4m3 per lane and MFMA
+  static constexpr int kInVec = 8, kWVec = 16;
+  static constexpr int kPad = 16, kPlanes = 1, kGroup = 16;
+};
+template <>
+struct ConvTraits<5> : ConvTraits<4> {  // e4m3 hi + lo planes
+  static constexpr int kPlanes = 2;
+};
 
-// 16-bit activations in HBM (bf16 or fp16)
-constexpr bool half_store(int mode) { return mode == 1 || mode == 3; }
+// 16-bit activations in HBM (bf16 or fp16, also behind the e4m3 modes)
+constexpr bool half_store(int mode) { return mode == 1 || mode == 3 || mode == 4 || mode == 5; }
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// accumulator -> layer sum: the e4m3 modes multiply by the output channel's weight scale
+template <int MODE>
+__device__ inline float scaled(float acc, float ws) {
+  if constexpr (MODE == 4 || MODE == 5) return acc * ws;
+  else return acc;
+}
 
 template <int MODE, int BM, int CK, int R, bool RGBDA>
 __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
@@ -187,7 +248,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   const size_t wrow0 = ((size_t)co0 * 9 + pw0) * a.cin_pad + qw;
   const size_t wstep = (size_t)PPW * a.cin_pad;
   const WT *wsrc = static_cast<const WT *>(a.w) + wrow0;
-  const WT *wsrc_lo = MODE == 2 ? static_cast<const WT *>(a.w_lo) + wrow0 : nullptr;
+  const WT *wsrc_lo = T::kPlanes == 2 ? static_cast<const WT *>(a.w_lo) + wrow0 : nullptr;
   constexpr int NWV = NWR * T::kPlanes;
 
   auto fetch = [&](int ci, uint4 (&pin)[NIN], uint4 (&pw)[NWV]) {
@@ -230,7 +291,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     for (int k = 0; k < NWR; ++k) {
       const bool ok = (k + 1) * PPW <= WROWS || pw0 + k * PPW < WROWS;
       pw[k] = ok ? *reinterpret_cast<const uint4 *>(wsrc + k * wstep + ci) : make_uint4(0u, 0u, 0u, 0u);
-      if constexpr (MODE == 2)
+      if constexpr (T::kPlanes == 2)
         pw[NWR + k] = ok ? *reinterpret_cast<const uint4 *>(wsrc_lo + k * wstep + ci) : make_uint4(0u, 0u, 0u, 0u);
     }
   };
@@ -248,6 +309,10 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         const uint32_t l23 = pack_bf16x2(f[2] - __uint_as_float(h23 << 16), f[3] - __uint_as_float(h23 & 0xFFFF0000u));
         *reinterpret_cast<uint2 *>(&s_in[li]) = make_uint2(h01, h23);
         *reinterpret_cast<uint2 *>(&s_in[INP + li]) = make_uint2(l01, l23);
+      } else if constexpr (MODE == 4 || MODE == 5) {
+        // 8 float16 channels -> 8 e4m3 bytes (plane 0) [+ 8 e4m3 remainders (plane 1)]
+        *reinterpret_cast<uint2 *>(&s_in[li]) = f16x8_to_e4m3<false>(pin[k]);
+        if constexpr (MODE == 5) *reinterpret_cast<uint2 *>(&s_in[INP + li]) = f16x8_to_e4m3<true>(pin[k]);
       } else {
         *reinterpret_cast<uint4 *>(&s_in[li]) = pin[k];
       }
@@ -257,7 +322,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
       if (!((k + 1) * PPW <= WROWS || pw0 + k * PPW < WROWS)) continue;
       const int li = (pw0 + k * PPW) * S + qw;
       *reinterpret_cast<uint4 *>(&s_w[li]) = pw[k];
-      if constexpr (MODE == 2) *reinterpret_cast<uint4 *>(&s_w[WP + li]) = pw[NWR + k];
+      if constexpr (T::kPlanes == 2) *reinterpret_cast<uint4 *>(&s_w[WP + li]) = pw[NWR + k];
     }
   };
 
@@ -277,8 +342,9 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   // one step = one horizontal tap offset dx of one channel group: the
   // fragments of step s + 1 are read from LDS while the MFMAs of step s run
   constexpr int NSTEP = (CK / G) * 3;
+  using FragT = typename T::Frag;
   struct Frags {
-    uint4 a[T::kPlanes][MB][3], b[T::kPlanes][R + 2];
+    FragT a[T::kPlanes][MB][3], b[T::kPlanes][R + 2];
   };
   auto load_frags = [&](int st, Frags &f) {
     const int g = st / 3, dx = st - 3 * g;
@@ -289,9 +355,9 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy)
-          f.a[p][mb][dy] = *reinterpret_cast<const uint4 *>(ag + p * WP + (mb * 32 * 9 + dy * 3 + dx) * S);
+          f.a[p][mb][dy] = *reinterpret_cast<const FragT *>(ag + p * WP + (mb * 32 * 9 + dy * 3 + dx) * S);
 #pragma unroll
-      for (int i = 0; i < R + 2; ++i) f.b[p][i] = *reinterpret_cast<const uint4 *>(bg + p * INP + (i * LW + dx) * S);
+      for (int i = 0; i < R + 2; ++i) f.b[p][i] = *reinterpret_cast<const FragT *>(bg + p * INP + (i * LW + dx) * S);
     }
   };
   auto mma = [&](const Frags &f) {
@@ -316,6 +382,16 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
           } else if constexpr (MODE == 3) {
             acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(f.a[0][mb][dy]), as_f16x8(f.b[0][r + dy]),
                                                                 acc[mb][r], 0, 0, 0);
+          } else if constexpr (MODE == 4) {
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(as_i64(f.a[0][mb][dy]), as_i64(f.b[0][r + dy]),
+                                                                    acc[mb][r], 0, 0, 0);
+          } else if constexpr (MODE == 5) {
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(as_i64(f.a[1][mb][dy]), as_i64(f.b[0][r + dy]),
+                                                                    acc[mb][r], 0, 0, 0);
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(as_i64(f.a[0][mb][dy]), as_i64(f.b[1][r + dy]),
+                                                                    acc[mb][r], 0, 0, 0);
+            acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(as_i64(f.a[0][mb][dy]), as_i64(f.b[0][r + dy]),
+                                                                    acc[mb][r], 0, 0, 0);
           } else {
             const int P1 = T::kPlanes - 1;  // lo plane
             acc[mb][r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(f.a[P1][mb][dy]), as_bf16x8(f.b[0][r + dy]),
@@ -354,7 +430,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
       }
       // scheduler strategy for MFMA / LDS-read interleaving (measured: 1 for
       // bf16, 0 for the three-pass split mode)
-      if constexpr (half_store(MODE)) __builtin_amdgcn_iglp_opt(1);
+      if constexpr (MODE == 1 || MODE == 3 || MODE == 4) __builtin_amdgcn_iglp_opt(1);
       else __builtin_amdgcn_iglp_opt(0);
     }
   };
@@ -392,9 +468,14 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
           if (c < a.cout) {
             const float4 b = *reinterpret_cast<const float4 *>(a.bias + c);
             const float bb[4] = {b.x, b.y, b.z, b.w};
+            float ws[4] = {1.f, 1.f, 1.f, 1.f};
+            if constexpr (MODE == 4 || MODE == 5) {
+              const float4 w4 = *reinterpret_cast<const float4 *>(a.wscale + c);
+              ws[0] = w4.x; ws[1] = w4.y; ws[2] = w4.z; ws[3] = w4.w;
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float v = fmaxf(acc[mb][r][4 * j + i] + bb[i], 0.f);
+              const float v = fmaxf(scaled<MODE>(acc[mb][r][4 * j + i], ws[i]) + bb[i], 0.f);
               s0 = fmaf(a.head_w[c + i], v, s0);
               s1 = fmaf(a.head_w[a.cout + c + i], v, s1);
               s2 = fmaf(a.head_w[2 * a.cout + c + i], v, s2);
@@ -441,11 +522,16 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
       if (c >= a.cout) continue;
       const float4 b = *reinterpret_cast<const float4 *>(a.bias + c);
       const float bb[4] = {b.x, b.y, b.z, b.w};
+      float ws[4] = {1.f, 1.f, 1.f, 1.f};
+      if constexpr (MODE == 4 || MODE == 5) {
+        const float4 w4 = *reinterpret_cast<const float4 *>(a.wscale + c);
+        ws[0] = w4.x; ws[1] = w4.y; ws[2] = w4.z; ws[3] = w4.w;
+      }
       float v[R][4];
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[r][i] = fmaxf(acc[mb][r][4 * j + i] + bb[i], 0.f);
+        for (int i = 0; i < 4; ++i) v[r][i] = fmaxf(scaled<MODE>(acc[mb][r][4 * j + i], ws[i]) + bb[i], 0.f);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if constexpr (kStage) {
@@ -1007,7 +1093,11 @@ hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s)
   if constexpr (MODE == 0) {
     if (ck == 8) return wide ? conv_launch<0, 64, 8, 2>(a, cout_pad, s) : conv_launch<0, 32, 8, 2>(a, cout_pad, s);
     return (wide && !small) ? conv_launch<0, 64, 16, 2>(a, cout_pad, s) : conv_launch<0, 32, 16, 2>(a, cout_pad, s);
-  } else if constexpr (half_store(MODE)) {
+  } else if constexpr (MODE == 2 || MODE == 5) {
+    if (ck < 16) return hipErrorInvalidValue;
+    if (wide) return conv_launch<MODE, 64, 16, 2>(a, cout_pad, s);
+    return conv_launch<MODE, 32, 16, 2>(a, cout_pad, s);
+  } else {
     if (ck < 16) return hipErrorInvalidValue;
     if (wide && !small)
       return ck == 32 ? conv_launch<MODE, 64, 32, 2>(a, cout_pad, s) : conv_launch<MODE, 64, 16, 2>(a, cout_pad, s);
@@ -1018,10 +1108,6 @@ hipError_t conv_dispatch(const ConvArgs &a, int ck, int cout_pad, hipStream_t s)
     // the layer with the fused head: 16-channel chunks measured faster (the same sums in the same order)
     return ck == 32 && !head ? conv_launch<MODE, 32, 32, 2>(a, cout_pad, s)
                              : conv_launch<MODE, 32, 16, 2>(a, cout_pad, s);
-  } else {
-    if (ck < 16) return hipErrorInvalidValue;
-    if (wide) return conv_launch<2, 64, 16, 2>(a, cout_pad, s);
-    return conv_launch<2, 32, 16, 2>(a, cout_pad, s);
   }
 }
 
@@ -1033,7 +1119,7 @@ hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, in
   const int nb = (npix + 255) / 256;
   if (p == Prec::BF16)
     pack_kernel<1, false><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
-  else if (p == Prec::FP16)
+  else if (p == Prec::FP16 || p == Prec::FP8 || p == Prec::FP8X3)  // float16 activations
     pack_kernel<3, false><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
   else if (p == Prec::F32)
     pack_kernel<0, true><<<nb, 256, 0, s>>>(depth, rgba, npix, cpad, x);
@@ -1046,7 +1132,7 @@ hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s) {
   const ConvLayer &L = *c.layer;
   ConvArgs a{c.in0, c.in1, c.C0, c.C1, c.H, c.W, L.w, L.w_lo, L.bias, L.cout, L.cin_pad, c.out, c.out_pool,
              c.head_w, c.head_b, c.head_out, c.batch < 1 ? 1 : c.batch, c.in0_bs, c.in1_bs, c.out_bs, c.pool_bs,
-             c.head_outs, c.rgbda_depth, c.rgbda_rgba, static_cast<const float *>(L.wu)};
+             c.head_outs, c.rgbda_depth, c.rgbda_rgba, static_cast<const float *>(L.wu), L.wscale};
   const bool head = c.head_out || c.head_outs;
   if (head && (L.cout_pad > 64 || c.out_pool)) return hipErrorInvalidValue;
   if (c.rgbda_depth && (!c.rgbda_rgba || c.C1 != 0 || c.batch > 1)) return hipErrorInvalidValue;
@@ -1062,6 +1148,8 @@ hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s) {
     case Prec::BF16: return conv_dispatch<1>(a, ck, L.cout_pad, s);
     case Prec::BF16X3: return conv_dispatch<2>(a, ck, L.cout_pad, s);
     case Prec::FP16: return conv_dispatch<3>(a, ck, L.cout_pad, s);
+    case Prec::FP8: return L.wscale ? conv_dispatch<4>(a, ck, L.cout_pad, s) : hipErrorInvalidValue;
+    case Prec::FP8X3: return L.wscale && L.w_lo ? conv_dispatch<5>(a, ck, L.cout_pad, s) : hipErrorInvalidValue;
     default: break;
   }
   return hipErrorInvalidValue;
@@ -1073,7 +1161,7 @@ hipError_t launch_head(const void *x, int C, int H, int W, const ConvLayer &head
   const float *w = static_cast<const float *>(head.w);
   if (p == Prec::BF16)
     head_kernel<1><<<nb, 256, 0, s>>>(x, C, npix, w, head.bias, out);
-  else if (p == Prec::FP16)
+  else if (p == Prec::FP16 || p == Prec::FP8 || p == Prec::FP8X3)  // float16 activations
     head_kernel<3><<<nb, 256, 0, s>>>(x, C, npix, w, head.bias, out);
   else
     head_kernel<0><<<nb, 256, 0, s>>>(x, C, npix, w, head.bias, out);

@@ -30,6 +30,7 @@ LNR_BF16 = 1
 LNR_FP8_E4M3 = 2
 LNR_BF16X3 = 3
 LNR_FP16 = 4
+LNR_FP8_E4M3X3 = 5
 
 LNR_RENDER_NO_CULL = 1
 LNR_RENDER_COUNT_ATOMICS = 2

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import FP16, FP32, BF16X3
+from tests.gpu_util import FP16, FP32, BF16X3, FP8_E4M3X3
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_cloud_and_network_loads_free_everything_on_failure(lnr, room_scene):
         fails += 1
     assert fails >= 5
     blob = synth.make_unet_blob((16, 32), seed=0)
-    for prec in (FP32, BF16X3, FP16):
+    for prec in (FP32, BF16X3, FP16, FP8_E4M3X3):
         fails = 0
         for _ in _sweep(lnr, ctx, lambda: lnr.lnr_unet_load(ctx, blob, prec)):
             assert lnr.lnr_allocated_bytes(ctx) == base
@@ -148,7 +148,11 @@ def test_server_rejects_a_session_too_small_for_its_filter_levels(lnr, room_clou
     lnr.lnr_server_destroy(srv)
 
 
-def test_fp8_precision_is_declared_but_not_built(lnr, ctx):
-    with pytest.raises(lnr.LnrError) as e:
-        lnr.lnr_unet_load(ctx, synth.make_unet_blob((16, 32), seed=0), lnr.LNR_FP8_E4M3)
-    assert e.value.status == lnr.LNR_E_UNSUPPORTED
+def test_unknown_precision_is_rejected(lnr, ctx):
+    blob = synth.make_unet_blob((16, 32), seed=0)
+    for prec in (6, 99, -1):
+        with pytest.raises(lnr.LnrError) as e:
+            lnr.lnr_unet_load(ctx, blob, prec)
+        assert e.value.status == lnr.LNR_E_INVALID_ARG
+    for prec in (lnr.LNR_FP8_E4M3, lnr.LNR_FP8_E4M3X3):
+        lnr.lnr_unet_destroy(lnr.lnr_unet_load(ctx, blob, prec))
