@@ -268,7 +268,9 @@ def serve_bench(L, scene, cloud, blob, seconds, n_sessions=64, seed=0, budget=32
     drawn from {640x480, 1280x720, 1920x1080}, Poisson arrivals at U(30, 90) Hz
     per session, bf16 U-Net, admitted under an HBM budget; continuous batching
     of same-resolution requests across sessions.  Latency = host time from
-    submit to the poll that sees the frame finished."""
+    submit to the poll that sees the frame finished; a request replaced by a
+    newer camera of its session before it ran is superseded, and its wait
+    (submit to the poll that reports it) is reported separately."""
     import numpy as np
     import synth
     rng = np.random.default_rng(seed)
@@ -294,18 +296,16 @@ def serve_bench(L, scene, cloud, blob, seconds, n_sessions=64, seed=0, budget=32
         sess.append({"sid": sid, "w": w, "h": h, "rate": rate, "cams": cams, "k": 0,
                      "next": float(rng.exponential(1.0 / rate))})
     submit_t = {}
-    lat, batches, per_res = [], [], {}
-    superseded = 0
+    lat, sup_wait, batches, per_res = [], [], [], {}
     submitted = 0
     t0 = time.perf_counter()
     tag = 0
 
     def drain_results(now):
-        nonlocal superseded
         for r in L.lnr_server_poll(srv):
             t_sub, res = submit_t.pop(r["tag"])
             if r["superseded"]:
-                superseded += 1
+                sup_wait.append(now - t_sub)
                 continue
             lat.append(now - t_sub)
             batches.append(r["batch"])
@@ -335,18 +335,40 @@ def serve_bench(L, scene, cloud, blob, seconds, n_sessions=64, seed=0, budget=32
             break
     elapsed = time.perf_counter() - t0
     lat_ms = np.array(lat) * 1000.0
+    sup_ms = np.array(sup_wait) * 1000.0
     done = len(lat)
     px = sum(int(k.split("x")[0]) * int(k.split("x")[1]) * v for k, v in per_res.items())
+
+    def pct(v, q):
+        return round(float(np.percentile(v, q)), 3) if len(v) else None
+
+    L.lnr_server_destroy(srv)
     return {
-        "sessions_admitted": len(sess), "sessions_refused": refused, "seconds_of_arrivals": round(t_end, 2),
-        "requests": submitted, "completed": done, "superseded": superseded,
+        "sessions": n_sessions, "sessions_admitted": len(sess), "sessions_refused": refused,
+        "seconds_of_arrivals": round(t_end, 2), "offered_requests_per_s": round(submitted / t_end, 1),
+        "requests": submitted, "completed": done, "superseded": len(sup_wait),
+        "superseded_fraction": round(len(sup_wait) / max(1, submitted), 4),
         "frames_per_s": round(done / elapsed, 1), "megapixels_per_s": round(px / elapsed / 1e6, 1),
-        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3) if done else None,
-                       "p99": round(float(np.percentile(lat_ms, 99)), 3) if done else None},
+        "latency_ms": {"p50": pct(lat_ms, 50), "p99": pct(lat_ms, 99)},
+        "superseded_wait_ms": {"p50": pct(sup_ms, 50), "p99": pct(sup_ms, 99)},
         "mean_batch": round(float(np.mean(batches)), 2) if batches else None,
         "frames_by_resolution": per_res, "budget_bytes": budget, "max_batch": max_batch, "lanes": lanes,
-        "precision": "bf16", "offered_requests_per_s": round(sum(ss["rate"] for ss in sess), 1),
+        "precision": "bf16",
     }
+
+
+def serve_sweep(L, scene, cloud, blob, seconds, counts=(8, 16, 32, 64)):
+    """The serving workload at several session counts (the same seeded
+    sessions, the first n of them): throughput, latency and superseded
+    fraction against offered load."""
+    out = []
+    for n in counts:
+        r = serve_bench(L, scene, cloud, blob, seconds, n_sessions=n)
+        log(f"serving {n} sessions: {r['frames_per_s']} frames/s of {r['offered_requests_per_s']} requests/s offered, "
+            f"superseded {100 * r['superseded_fraction']:.1f}%, p50 {r['latency_ms']['p50']} ms, "
+            f"p99 {r['latency_ms']['p99']} ms")
+        out.append(r)
+    return out
 
 
 def largest_scene(args):
@@ -537,7 +559,8 @@ def main():
     ap.add_argument("--pipelined", action="store_true",
                     help="overlap the next frame's projection and filter (second stream and context) with the "
                          "current frame's U-Net (default: frames one after the other on one stream)")
-    ap.add_argument("--serve-seconds", type=float, default=5.0, help="serving run length (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="serving run length per session count of the sweep (0 = skip)")
     ap.add_argument("--mode", default="frames", choices=["frames", "copy", "counters", "precision-tier", "largest"],
                     help="copy: only a plain 1 GiB device copy (calibrates HBM byte counters); "
                          "counters: summarise rocprofv3 FETCH_SIZE/WRITE_SIZE csv files (no GPU); "
@@ -858,10 +881,12 @@ def main():
     except Exception:
         pass
     if args.serve_seconds > 0:
-        log(f"serving 64 sessions for {args.serve_seconds} s ...")
-        line["serving"] = serve_bench(L, scene, cloud, blob, args.serve_seconds)
-        log(f"serving: {line['serving']['frames_per_s']} frames/s, p50 {line['serving']['latency_ms']['p50']} ms, "
-            f"p99 {line['serving']['latency_ms']['p99']} ms")
+        log(f"serving 8, 16, 32 and 64 sessions, {args.serve_seconds} s each ...")
+        sweep = serve_sweep(L, scene, cloud, blob, args.serve_seconds)
+        line["serving"] = dict(sweep[-1])  # the 64-session workload
+        line["serving"]["sweep"] = [{k: r[k] for k in ("sessions", "offered_requests_per_s", "frames_per_s",
+                                                       "superseded_fraction", "latency_ms", "superseded_wait_ms",
+                                                       "mean_batch", "megapixels_per_s")} for r in sweep]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(scene, cams[0], blob, NL, FS, widths)
