@@ -157,6 +157,14 @@ __device__ inline void global_min(uint64_t *dst, uint64_t k, uint32_t &issued) {
   }
 }
 
+// floor(p / w) for 0 <= p < 4096 and 1 <= w <= 4096, by a float reciprocal:
+// the quotient of p + 1/2 is at least 1/(2w) from an integer, and the two
+// float roundings move it by at most (4096/w) 2^-23, which is less, so the
+// truncation lands on the same integer.  inv_w = 1.0f / w.
+__device__ inline uint32_t small_div(uint32_t p, float inv_w) {
+  return (uint32_t)(((float)p + 0.5f) * inv_w);
+}
+
 // Project the work item's points (thread t takes points t, t + 256, ...):
 // kk = key, (px, py) = pixel, px = ~0u if the point is not drawn; and the
 // screen rectangle [x0, x1] x [y0, y1] of the drawn points over the whole
@@ -248,10 +256,11 @@ __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict
     for (int q = 0; q < kPtsPerThread; ++q)
       if (px[q] != ~0u) atomicMin(&zb[(py[q] - y0) * bw + (px[q] - x0)], (unsigned long long)kk[q]);
     __syncthreads();
+    const float inv_bw = 1.0f / (float)bw;
     for (uint32_t p = tid; p < area; p += kThreads) {
       const uint64_t k = zb[p];
       if (k == ~0ull) continue;
-      const uint32_t ry = p / bw, rx = p - ry * bw;
+      const uint32_t ry = small_div(p, inv_bw), rx = p - ry * bw;
       global_min<COUNT>(key + (size_t)(y0 + ry) * cam.W + (x0 + rx), k, issued);
     }
   } else {
@@ -372,9 +381,10 @@ __global__ __launch_bounds__(kThreads) void bin_kernel(const float *__restrict__
   }
   __syncthreads();
   // pixel and key of an entry in slot p
+  const float inv_bw = 1.0f / (float)bw;
   auto decode = [&](uint32_t p, uint64_t e, uint32_t *gx, uint32_t *gy) -> uint64_t {
     if (dedup) {
-      const uint32_t ry = p / bw;
+      const uint32_t ry = small_div(p, inv_bw);
       *gy = y0 + ry;
       *gx = x0 + (p - ry * bw);
       return e;
