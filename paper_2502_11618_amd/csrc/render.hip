@@ -83,19 +83,44 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(const float *__restrict_
     }
     flags[c] = vis ? 1 : 0;
   }
-  // this cell's work items go to its bucket's queue: places are reserved per
-  // block in LDS, then with one global atomic per bucket
-  __shared__ uint32_t s_n[kDepthBuckets], s_base[kDepthBuckets];
-  if (threadIdx.x < kDepthBuckets) s_n[threadIdx.x] = 0;
-  __syncthreads();
+  // this cell's work items go to its bucket's queue.  Compaction: per depth
+  // bucket present in the wave, a wave-wide exclusive prefix (shuffle scan) of
+  // the lanes' work-item counts gives each visible cell its place within the
+  // wave's run; the wave runs are ordered within the block through LDS, and
+  // one global atomic per bucket and block reserves the block's places
+  constexpr int kWaves = kThreads / 64;
+  __shared__ uint32_t s_wave[kWaves][kDepthBuckets], s_base[kDepthBuckets];
+  const int wave = threadIdx.x >> 6;
   const uint32_t nch = vis ? (cnt + kSplatChunk - 1) / kSplatChunk : 0u;
-  const uint32_t local = nch ? atomicAdd(&s_n[bucket], nch) : 0u;
+  uint32_t present = nch ? (1u << bucket) : 0u;  // buckets of this wave's visible cells
+  for (int off = 32; off > 0; off >>= 1) present |= __shfl_xor(present, off, 64);
+  uint32_t local = 0;
+  for (int b = 0; b < kDepthBuckets; ++b) {
+    uint32_t tot = 0;
+    if (present & (1u << b)) {  // the same for the whole wave
+      const uint32_t v = bucket == b ? nch : 0u;
+      uint32_t incl = v;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+      }
+      if (v) local = incl - v;
+      tot = __shfl(incl, 63, 64);
+    }
+    if (lane == 0) s_wave[wave][b] = tot;
+  }
   __syncthreads();
-  if (threadIdx.x < kDepthBuckets && s_n[threadIdx.x])
-    s_base[threadIdx.x] = atomicAdd(&counters[4 + threadIdx.x], s_n[threadIdx.x]);
+  if (threadIdx.x < kDepthBuckets) {
+    uint32_t sum = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) sum += s_wave[w][threadIdx.x];
+    s_base[threadIdx.x] = sum ? atomicAdd(&counters[4 + threadIdx.x], sum) : 0u;
+  }
   __syncthreads();
   if (nch) {
-    const uint32_t pos = s_base[bucket] + local;
+    uint32_t pos = s_base[bucket] + local;
+    for (int w = 0; w < wave; ++w) pos += s_wave[w][bucket];
     for (uint32_t k = 0; k < nch; ++k) {
       const uint32_t off = k * kSplatChunk;
       chunks[(size_t)bucket * cap + pos + k] = make_uint2(start + off, min(kSplatChunk, cnt - off));

@@ -4,10 +4,10 @@ bench times: 20M points of the seeded multi-room scene in 1 m cells, the
 filter_strength 0.5, U-Net widths 32/64/128/256.
 
 Projection and filter are compared on whole frames, bit for bit.  The U-Net is
-compared on 64x64 windows that the float64 oracle computes one by one on a
-crop grown by the receptive margin (corners and edges included, so the ragged
-tile tails of every level are covered), with the bounds of the small-size
-tests.  Batched serving at this size must give each frame exactly what it
+compared on six 64x64 windows that the float64 oracle computes one by one on
+a crop grown by the receptive margin (corners, so the ragged tile tails of
+every level are covered; two windows across the tile seams of every level),
+with the bounds of the small-size tests.  Batched serving at this size must give each frame exactly what it
 gives alone."""
 
 import numpy as np
@@ -30,10 +30,15 @@ UNET_FRAMES = (0, 60)
 
 
 def _windows(frame):
+    """Corners (the ragged tile tails of every level), the centre, a random
+    window, and two windows that straddle the convolution tile seams of every
+    level: a workgroup tile is 8 rows x 32 columns of level-l pixels, i.e.
+    8 * 2^l by 32 * 2^l full-resolution pixels, so rows 128 and 512 and
+    columns 256 and 1024 are seams at levels 0-3 (and 0-4 for the rows)."""
     rng = np.random.default_rng(1000 + frame)
     y, x = int(rng.integers(0, H - 64)), int(rng.integers(0, W - 64))
     return [(0, 64, 0, 64), (H - 64, H, W - 64, W), (H // 2 - 32, H // 2 + 32, W // 2 - 32, W // 2 + 32),
-            (y, y + 64, x, x + 64)]
+            (y, y + 64, x, x + 64), (96, 160, 224, 288), (480, 544, 992, 1056)]
 
 
 @pytest.fixture(scope="module")

@@ -49,7 +49,7 @@ def _serve_all(lnr, srv, sids, cams_per_session, frames):
     return results
 
 
-@pytest.mark.parametrize("prec,graphs", [(0, True), (1, True), (3, False), (4, True)])
+@pytest.mark.parametrize("prec,graphs", [(0, True), (1, True), (3, False), (4, True), (5, True), (2, False)])
 def test_mixed_batches_equal_alone(lnr, ctx, room_scene, room_cloud, room_grid, prec, graphs):
     blob = synth.make_unet_blob((16, 32, 64), seed=0)
     net = lnr.lnr_unet_load(ctx, blob, prec)
