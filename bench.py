@@ -371,6 +371,49 @@ def serve_sweep(L, scene, cloud, blob, seconds, counts=(8, 16, 32, 64)):
     return out
 
 
+def multiview_render(L, ctx, cloud, cams, W, H, batch, nbatch):
+    """Projection of one batch of views, view by view (the default tiled splat,
+    each view reading its visible cells' points) against lnr_render_views (one
+    pass per 8 views, each point of a cell visible in any of them read once):
+    time per batch by HIP events on the stream both run on, points read, and
+    whether every image is the same bit for bit."""
+    import numpy as np
+    import torch
+
+    imgs = [L.Image(H, W) for _ in range(batch)]
+    ref = [L.Image(H, W) for _ in range(batch)]
+    single_ms, multi_ms, read_single, read_multi, same = [], [], [], [], True
+    for b in range(1 + nbatch):  # batch 0 warms up
+        bc = [cams[(b * batch + v) % len(cams)] for v in range(batch)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        for v in range(batch):
+            L.lnr_render(ctx, cloud, bc[v], ref[v])
+        e[1].record()
+        L.lnr_render_views(ctx, cloud, bc, imgs)
+        e[2].record()
+        torch.cuda.synchronize()
+        if b == 0:
+            continue
+        single_ms.append(e[0].elapsed_time(e[1]))
+        multi_ms.append(e[1].elapsed_time(e[2]))
+        read_multi.append(L.lnr_render_stats(ctx)[1])
+        n = 0
+        for v in range(batch):
+            L.lnr_render(ctx, cloud, bc[v], ref[v])
+            torch.cuda.synchronize()
+            n += L.lnr_render_stats(ctx)[1]
+        read_single.append(n)
+        same = same and all(torch.equal(imgs[v].key, ref[v].key) and torch.equal(imgs[v].depth, ref[v].depth)
+                            and torch.equal(imgs[v].rgba, ref[v].rgba) for v in range(batch))
+    return {"views_per_batch": batch, "batches": nbatch,
+            "view_by_view_ms_per_batch": round(float(np.mean(single_ms)), 3),
+            "multi_view_ms_per_batch": round(float(np.mean(multi_ms)), 3),
+            "points_read_view_by_view": int(np.mean(read_single)),
+            "points_read_multi_view": int(np.mean(read_multi)),
+            "images_identical": bool(same)}
+
+
 def largest_scene(args):
     """The largest configuration: 300M points from 16 scans of an 80 x 60 x 10 m
     scene of 32 rooms (2 m cells); batches of 8 consecutive orbit-path views at
@@ -401,6 +444,14 @@ def largest_scene(args):
     cams = synth.orbit_path(scene, 120, W, H, FOV)
     prec_ids = {"fp32": L.LNR_FP32, "fp16": L.LNR_FP16, "bf16x3": L.LNR_BF16X3, "bf16": L.LNR_BF16,
                 "fp8x3": L.LNR_FP8_E4M3X3, "fp8": L.LNR_FP8_E4M3}
+    mv = multiview_render(L, ctx, cloud, cams, W, H, BATCH, NBATCH)
+    log(f"projection of a batch of {BATCH}: view by view {mv['view_by_view_ms_per_batch']} ms "
+        f"({mv['points_read_view_by_view']} points read), multi-view {mv['multi_view_ms_per_batch']} ms "
+        f"({mv['points_read_multi_view']} points read), identical: {mv['images_identical']}")
+    if args.projection_only:
+        print(json.dumps({"mode": "largest", "workload": "huge-300M-pts-16-scans-8x4K-batches", "points": scene.n,
+                          "multi_view_render": mv, "env": host_info()}), flush=True)
+        return
     nets = {p: L.lnr_unet_load(ctx, blob, i) for p, i in prec_ids.items()}
     img = L.Image(H, W)
     outs = [torch.empty((3, H, W), dtype=torch.float32, device="cuda") for _ in range(BATCH)]
@@ -480,7 +531,7 @@ def largest_scene(args):
                       "unet_flops_per_view": unet_flops,
                       "processed_points_per_view": {"mean": float(np.mean(proc)), "min": int(min(proc)),
                                                     "max": int(max(proc))},
-                      "results": res, "env": host_info()}), flush=True)
+                      "multi_view_render": mv, "results": res, "env": host_info()}), flush=True)
 
 
 def precision_tier(args):
@@ -574,6 +625,8 @@ def main():
                          "counters: summarise rocprofv3 FETCH_SIZE/WRITE_SIZE csv files (no GPU); "
                          "precision-tier: the 100M-point scene at 1080p and 1440p in every precision; "
                          "largest: the 300M-point scene, batches of 8 views at 3840x2160, 5-level U-Net")
+    ap.add_argument("--projection-only", action="store_true",
+                    help="largest mode: stop after comparing view-by-view and multi-view projection")
     ap.add_argument("--fetch-csv", help="counters mode: FETCH_SIZE counter_collection.csv of a frames run")
     ap.add_argument("--write-csv", help="counters mode: WRITE_SIZE counter_collection.csv of a frames run")
     ap.add_argument("--copy-fetch-csv", help="counters mode: FETCH_SIZE csv of a copy run")

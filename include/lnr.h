@@ -182,6 +182,29 @@ lnr_status lnr_render(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *ca
  * a pixel may collect at most 2^24 points. */
 lnr_status lnr_render_soft(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cam, lnr_image *out,
                            float soft_eps, uint32_t flags, void *hip_stream);
+/* Render several views of one cloud (a batch of cameras, e.g. the views of
+ * one serving step), reading each point from device memory once per pass
+ * instead of once per view (Method, "Point Cloud Projection", applied to
+ * every camera of the batch).  outs[v] receives exactly what lnr_render of
+ * cams[v] alone writes, bit for bit, for every v.
+ *   cams, outs : HOST arrays of n_views cameras and images (the images'
+ *                buffers are device buffers, as for lnr_render); the views'
+ *                key buffers must not overlap (LNR_E_INVALID_ARG).
+ *   n_views    : 1..1024.  The views go in passes of up to 8: a pass culls
+ *                every grid cell against each of its views' frustums, and
+ *                the points of a cell visible in any of them are loaded once
+ *                and drawn into each view whose frustum the cell meets.
+ *   flags      : 0 or LNR_RENDER_NO_CULL.  The z-buffers are the images' key
+ *                buffers, lowered with 64-bit atomicMin after an on-chip
+ *                z-buffer per work item (LNR_RENDER_ATOMIC_SPLAT's method):
+ *                the screen-tiled splat would need its per-point scratch
+ *                once per view.
+ * Uses 16 bytes of context scratch per work item and depth bucket.
+ * lnr_render_stats then reports the last pass: cells visible in at least one
+ * of its views, and the points of those cells, each read once.  Errors as
+ * lnr_render, checked for every view before anything is enqueued. */
+lnr_status lnr_render_views(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cams, lnr_image *outs,
+                            int32_t n_views, uint32_t flags, void *hip_stream);
 /* Statistics of the last lnr_render on ctx; waits for ctx's last stream.
  * visible_cells: cells that passed the frustum test; processed_points:
  * points in those cells.  cull_flags_host (may be NULL): HOST uint8[n_cells]

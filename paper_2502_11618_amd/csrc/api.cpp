@@ -33,6 +33,7 @@ thread_local std::string g_create_error;
 struct Scratch {
   Buf flags, chunks, counters, pyramid, act, soft_acc;
   Buf recs, segs, sorted, tile_nseg, tile_off, tile_units, units;  // tiled splat
+  Buf views;                                                         // multi-view work items
 };
 
 }  // namespace
@@ -513,7 +514,7 @@ void context_free(lnr_context *ctx) {
   (void)hipDeviceSynchronize();
   for (Buf *b : {&ctx->sc.flags, &ctx->sc.chunks, &ctx->sc.counters, &ctx->sc.pyramid, &ctx->sc.act, &ctx->sc.soft_acc,
                  &ctx->sc.recs, &ctx->sc.segs, &ctx->sc.sorted, &ctx->sc.tile_nseg, &ctx->sc.tile_off,
-                 &ctx->sc.tile_units, &ctx->sc.units})
+                 &ctx->sc.tile_units, &ctx->sc.units, &ctx->sc.views})
     dfree(ctx, b->p, b->cap);
   for (auto &r : ctx->recs) {
     (void)hipEventDestroy(r.a);
@@ -716,6 +717,29 @@ static TiledSplatBufs tiled_bufs(Scratch &scr) {
                         static_cast<uint2 *>(scr.units.p)};
 }
 
+static SplatCam make_splat_cam(const lnr_camera *cam) {
+  SplatCam sc{};
+  std::memcpy(sc.P, cam->P, sizeof(sc.P));
+  sc.Wf = (float)cam->width;
+  sc.Hf = (float)cam->height;
+  sc.z_near = cam->z_near;
+  sc.z_far = cam->z_far;
+  sc.W = (uint32_t)cam->width;
+  return sc;
+}
+
+// checks of one render target against its camera
+static lnr_status check_target(lnr_context *ctx, const lnr_camera *cam, const lnr_image *out) {
+  std::string why;
+  if (!camera_ok(cam, &why)) return fail(ctx, LNR_E_INVALID_ARG, why);
+  if (!out->key || !out->depth || !out->rgba) return fail(ctx, LNR_E_INVALID_ARG, "image buffers must be non-NULL");
+  if (out->width != cam->width || out->height != cam->height)
+    return fail(ctx, LNR_E_INVALID_ARG, "image size differs from the camera's");
+  if (!aligned(out->key, 8) || !aligned(out->depth, 4) || !aligned(out->rgba, 4))
+    return fail(ctx, LNR_E_INVALID_ARG, "image buffers are misaligned");
+  return LNR_OK;
+}
+
 static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c, const lnr_camera *cam,
                               lnr_image *out, uint32_t flags, bool soft, float soft_eps, void *hip_stream) {
   if (!ctx) return LNR_E_INVALID_ARG;
@@ -724,15 +748,10 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   if (!c || !cam || !out) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
   if (flags & ~(LNR_RENDER_NO_CULL | LNR_RENDER_COUNT_ATOMICS | LNR_RENDER_ATOMIC_SPLAT))
     return fail(ctx, LNR_E_INVALID_ARG, "unknown render flags");
-  std::string why;
-  if (!camera_ok(cam, &why)) return fail(ctx, LNR_E_INVALID_ARG, why);
-  if (!out->key || !out->depth || !out->rgba) return fail(ctx, LNR_E_INVALID_ARG, "image buffers must be non-NULL");
-  if (out->width != cam->width || out->height != cam->height)
-    return fail(ctx, LNR_E_INVALID_ARG, "image size differs from the camera's");
-  if (!aligned(out->key, 8) || !aligned(out->depth, 4) || !aligned(out->rgba, 4))
-    return fail(ctx, LNR_E_INVALID_ARG, "image buffers are misaligned");
+  lnr_status st = check_target(ctx, cam, out);
+  if (st != LNR_OK) return st;
   if (c->ctx->device != ctx->device) return fail(ctx, LNR_E_INVALID_ARG, "cloud lives on another device");
-  lnr_status st = use_device(ctx);
+  st = use_device(ctx);
   if (st != LNR_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if ((st = ensure(ctx, scr.flags, c->d.n_cells)) != LNR_OK) return st;
@@ -742,13 +761,7 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   const uint32_t npix = (uint32_t)cam->width * (uint32_t)cam->height;
   uint32_t *counters = static_cast<uint32_t *>(scr.counters.p);
   const CullParams prm = make_cull_params(cam, (flags & LNR_RENDER_NO_CULL) != 0);
-  SplatCam sc{};
-  std::memcpy(sc.P, cam->P, sizeof(sc.P));
-  sc.Wf = (float)cam->width;
-  sc.Hf = (float)cam->height;
-  sc.z_near = cam->z_near;
-  sc.z_far = cam->z_far;
-  sc.W = (uint32_t)cam->width;
+  const SplatCam sc = make_splat_cam(cam);
   const bool count = (flags & LNR_RENDER_COUNT_ATOMICS) != 0;
   const bool atomic = count || (flags & LNR_RENDER_ATOMIC_SPLAT) != 0;
   const TiledSplatGrid tg = tiled_splat_grid((uint32_t)cam->width, (uint32_t)cam->height, c->d.n);
@@ -792,6 +805,68 @@ lnr_status lnr_render_soft(lnr_context *ctx, const lnr_cloud *c, const lnr_camer
                            float soft_eps, uint32_t flags, void *hip_stream) {
   if (!ctx) return LNR_E_INVALID_ARG;
   return render_impl(ctx, ctx->sc, c, cam, out, flags, true, soft_eps, hip_stream);
+}
+
+lnr_status lnr_render_views(lnr_context *ctx, const lnr_cloud *c, const lnr_camera *cams, lnr_image *outs,
+                            int32_t n_views, uint32_t flags, void *hip_stream) {
+  if (!ctx) return LNR_E_INVALID_ARG;
+  if (!c || !cams || !outs) return fail(ctx, LNR_E_INVALID_ARG, "NULL pointer argument");
+  if (n_views < 1 || n_views > kMaxRenderViews)
+    return fail(ctx, LNR_E_INVALID_ARG, "n_views must be in [1, " + std::to_string(kMaxRenderViews) + "]");
+  if (flags & ~LNR_RENDER_NO_CULL) return fail(ctx, LNR_E_INVALID_ARG, "unknown or unsupported render flags");
+  lnr_status st;
+  for (int v = 0; v < n_views; ++v)
+    if ((st = check_target(ctx, &cams[v], &outs[v])) != LNR_OK) return st;
+  // views that shared key buffers would mix their z-buffers
+  for (int v = 0; v < n_views; ++v) {
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(outs[v].key);
+    const uintptr_t a1 = a0 + 8ull * (uint64_t)outs[v].width * (uint64_t)outs[v].height;
+    for (int u = 0; u < v; ++u) {
+      const uintptr_t b0 = reinterpret_cast<uintptr_t>(outs[u].key);
+      const uintptr_t b1 = b0 + 8ull * (uint64_t)outs[u].width * (uint64_t)outs[u].height;
+      if (a0 < b1 && b0 < a1) return fail(ctx, LNR_E_INVALID_ARG, "two views' key buffers overlap");
+    }
+  }
+  if (c->ctx->device != ctx->device) return fail(ctx, LNR_E_INVALID_ARG, "cloud lives on another device");
+  if ((st = use_device(ctx)) != LNR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Scratch &scr = ctx->sc;
+  if ((st = ensure(ctx, scr.flags, c->d.n_cells)) != LNR_OK) return st;
+  if ((st = ensure(ctx, scr.views, 16ull * kDepthBuckets * std::max<uint32_t>(1, c->d.max_chunks))) != LNR_OK)
+    return st;
+  if ((st = ensure(ctx, scr.counters, 4 * kCounterWords)) != LNR_OK) return st;
+  uint32_t *counters = static_cast<uint32_t *>(scr.counters.p);
+  uint4 *items = static_cast<uint4 *>(scr.views.p);
+  const bool no_cull = (flags & LNR_RENDER_NO_CULL) != 0;
+  for (int g = 0; g < n_views; g += kViewsPerPass) {
+    const int n = std::min(kViewsPerPass, n_views - g);
+    ViewsCull vc{};
+    ViewsSplat vs{};
+    vc.n = vs.n = n;
+    for (int v = 0; v < n; ++v) {
+      const lnr_camera *cam = &cams[g + v];
+      const lnr_image &o = outs[g + v];
+      vc.v[v] = make_cull_params(cam, no_cull);
+      vs.cam[v] = make_splat_cam(cam);
+      vs.key[v] = o.key;
+      LNR_LAUNCH(ctx, "clear", s,
+                 launch_clear(o.key, (uint32_t)o.width * (uint32_t)o.height, counters, nullptr, 0u, s));
+    }
+    LNR_LAUNCH(ctx, "cull_views", s,
+               launch_cull_views(c->d, vc, static_cast<uint8_t *>(scr.flags.p), items, counters, s));
+    LNR_LAUNCH(ctx, "splat_views", s, launch_splat_views(c->d, items, counters, vs, s));
+    for (int v = 0; v < n; ++v) {
+      const lnr_image &o = outs[g + v];
+      LNR_LAUNCH(ctx, "resolve", s,
+                 launch_resolve(o.key, c->d.rgbx, o.depth, reinterpret_cast<uint32_t *>(o.rgba),
+                                (uint32_t)o.width * (uint32_t)o.height, s));
+    }
+  }
+  ctx->last_stream = s;
+  ctx->rendered = true;
+  ctx->counted = false;
+  ctx->last_cells = c->d.n_cells;
+  return LNR_OK;
 }
 
 lnr_status lnr_render_stats(lnr_context *ctx, uint64_t *visible_cells, uint64_t *processed_points,
@@ -1285,7 +1360,8 @@ void server_release(lnr_server *srv) {
     for (auto &g : l.graphs) (void)hipGraphExecDestroy(g.second);
     for (auto g : l.graph_defs) (void)hipGraphDestroy(g);
     for (Buf *b : {&l.sc.flags, &l.sc.chunks, &l.sc.counters, &l.sc.pyramid, &l.sc.act, &l.sc.soft_acc, &l.sc.recs,
-                   &l.sc.segs, &l.sc.sorted, &l.sc.tile_nseg, &l.sc.tile_off, &l.sc.tile_units, &l.sc.units})
+                   &l.sc.segs, &l.sc.sorted, &l.sc.tile_nseg, &l.sc.tile_off, &l.sc.tile_units, &l.sc.units,
+                   &l.sc.views})
       dfree(ctx, b->p, b->cap);
     if (l.head_outs_dev) dfree(ctx, l.head_outs_dev, 8ull * 16);
     if (l.head_outs_host) (void)hipHostFree(l.head_outs_host);

@@ -57,6 +57,21 @@ struct SplatCam {
   uint32_t W;
 };
 
+// Multi-view render: views per pass over the cloud.  The per-view cameras
+// travel as kernel arguments (a pass's culling parameters take 2.8 KB).
+constexpr int kViewsPerPass = 8;
+constexpr int kMaxRenderViews = 1024;  // views per lnr_render_views call
+struct ViewsCull {
+  CullParams v[kViewsPerPass];
+  int n;
+};
+struct ViewsSplat {
+  SplatCam cam[kViewsPerPass];
+  uint64_t *key[kViewsPerPass];
+  int n;
+};
+static_assert(sizeof(ViewsCull) + 64 <= 4096, "kernel arguments stay within 4 KB");
+
 // counters written by the render kernels: [0] chunks, [1] visible cells,
 // [2..3] processed points (u64), [4 + b] chunks queued in depth bucket b,
 // [kAtomicWord] z-buffer atomics issued (counting renders only)
@@ -124,6 +139,13 @@ hipError_t launch_cull(const CloudDev &c, const CullParams &prm, uint8_t *flags,
 // z-buffer atomics issued to counters[kAtomicWord]
 hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counters, const SplatCam &cam,
                         uint64_t *key, bool count_atomics, hipStream_t s);
+// several views in one pass: work items (start, count, view mask, 0) queued
+// as launch_cull queues its chunks, then one splat that reads each work
+// item's points once for all the views of its mask
+hipError_t launch_cull_views(const CloudDev &c, const ViewsCull &prm, uint8_t *flags, uint4 *items, uint32_t *counters,
+                             hipStream_t s);
+hipError_t launch_splat_views(const CloudDev &c, const uint4 *items, const uint32_t *counters, const ViewsSplat &vs,
+                              hipStream_t s);
 // throughput probe: grid x 256 threads x iters 64-bit atomicMin on buf[n_slots]
 // (pattern 0: pseudo-random words; 1: one word per wave, consecutive waves
 // consecutive words)

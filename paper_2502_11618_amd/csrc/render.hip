@@ -34,64 +34,49 @@ __global__ __launch_bounds__(kThreads) void clear_kernel(uint64_t *__restrict__ 
   if (blockIdx.x == 0 && threadIdx.x < kCounterWords) counters[threadIdx.x] = 0;
 }
 
-// One lane per cell.  A non-empty cell is visible unless some half-space's
-// maximum over the cell's box is below -slack (all in double, in the order
-// below).  Visible cells are cut into splat work items of at most kSplatChunk
-// points, queued in the depth bucket of the cell's centre; the totals are
-// reduced per wave with one atomic per wave.
-__global__ __launch_bounds__(kThreads) void cull_kernel(const float *__restrict__ aabb,
-                                                        const uint32_t *__restrict__ cell_start, uint32_t n_cells,
-                                                        CullParams prm, uint8_t *__restrict__ flags,
-                                                        uint2 *__restrict__ chunks, uint32_t cap,
-                                                        uint32_t *__restrict__ counters) {
-  const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  uint32_t start = 0, cnt = 0;
-  bool vis = false;
-  int bucket = 0;
-  if (c < n_cells) {
-    start = cell_start[c];
-    cnt = cell_start[c + 1] - start;
-    if (cnt > 0) {
-      const double lo0 = aabb[6ull * c + 0], lo1 = aabb[6ull * c + 1], lo2 = aabb[6ull * c + 2];
-      const double hi0 = aabb[6ull * c + 3], hi1 = aabb[6ull * c + 4], hi2 = aabb[6ull * c + 5];
-      if (prm.no_cull) {
-        vis = true;
-      } else {
-        const double mx0 = fmax(fabs(lo0), fabs(hi0));
-        const double mx1 = fmax(fabs(lo1), fabs(hi1));
-        const double mx2 = fmax(fabs(lo2), fabs(hi2));
-        double S[3];
-        for (int r = 0; r < 3; ++r)
-          S[r] = ((prm.absP[r][0] * mx0 + prm.absP[r][1] * mx1) + prm.absP[r][2] * mx2) + prm.absP[r][3];
-        const double slack = 0x1p-20 * ((S[0] + S[1]) + prm.wh1 * S[2]);
-        vis = true;
-        for (int h = 0; h < 6; ++h) {
-          const double *k = prm.hs[h];
-          const double m =
-              ((fmax(k[0] * lo0, k[0] * hi0) + fmax(k[1] * lo1, k[1] * hi1)) + fmax(k[2] * lo2, k[2] * hi2)) + k[3];
-          if (m < -slack) vis = false;
-        }
-      }
-      if (vis) {
-        // camera depth of the box centre -> bucket
-        const double cw = ((prm.wrow[0] * (0.5 * (lo0 + hi0)) + prm.wrow[1] * (0.5 * (lo1 + hi1))) +
-                           prm.wrow[2] * (0.5 * (lo2 + hi2))) + prm.wrow[3];
-        const float q = cw > prm.z_near ? kBucketsPerOctave * __log2f((float)(cw / prm.z_near)) : 0.f;
-        bucket = q >= (float)(kDepthBuckets - 1) ? kDepthBuckets - 1 : (int)q;
-      }
+// Conservative visibility of a cell's box [lo, hi] for one camera: the box is
+// visible unless some half-space's maximum over it is below -slack (all in
+// double, in the order below).  If visible, *bucket is the depth bucket of the
+// box centre.
+__device__ inline bool cell_visible(const CullParams &prm, double lo0, double lo1, double lo2, double hi0,
+                                    double hi1, double hi2, int *bucket) {
+  bool vis = true;
+  if (!prm.no_cull) {
+    const double mx0 = fmax(fabs(lo0), fabs(hi0));
+    const double mx1 = fmax(fabs(lo1), fabs(hi1));
+    const double mx2 = fmax(fabs(lo2), fabs(hi2));
+    double S[3];
+    for (int r = 0; r < 3; ++r)
+      S[r] = ((prm.absP[r][0] * mx0 + prm.absP[r][1] * mx1) + prm.absP[r][2] * mx2) + prm.absP[r][3];
+    const double slack = 0x1p-20 * ((S[0] + S[1]) + prm.wh1 * S[2]);
+    for (int h = 0; h < 6; ++h) {
+      const double *k = prm.hs[h];
+      const double m =
+          ((fmax(k[0] * lo0, k[0] * hi0) + fmax(k[1] * lo1, k[1] * hi1)) + fmax(k[2] * lo2, k[2] * hi2)) + k[3];
+      if (m < -slack) vis = false;
     }
-    flags[c] = vis ? 1 : 0;
   }
-  // this cell's work items go to its bucket's queue.  Compaction: per depth
-  // bucket present in the wave, a wave-wide exclusive prefix (shuffle scan) of
-  // the lanes' work-item counts gives each visible cell its place within the
-  // wave's run; the wave runs are ordered within the block through LDS, and
-  // one global atomic per bucket and block reserves the block's places
+  if (vis) {
+    // camera depth of the box centre -> bucket
+    const double cw = ((prm.wrow[0] * (0.5 * (lo0 + hi0)) + prm.wrow[1] * (0.5 * (lo1 + hi1))) +
+                       prm.wrow[2] * (0.5 * (lo2 + hi2))) + prm.wrow[3];
+    const float q = cw > prm.z_near ? kBucketsPerOctave * __log2f((float)(cw / prm.z_near)) : 0.f;
+    *bucket = q >= (float)(kDepthBuckets - 1) ? kDepthBuckets - 1 : (int)q;
+  }
+  return vis;
+}
+
+// Queue places for this lane's nch work items in queue `bucket`: the first
+// one's place within that queue.  Compaction without LDS atomics: per depth
+// bucket present in the wave, a wave-wide exclusive prefix (shuffle scan) of
+// the lanes' work-item counts places each cell within the wave's run; the
+// runs of the block's waves follow each other in wave order through LDS, and
+// one global atomic per bucket and block reserves the block's run.  Every
+// thread of the block calls it (block barriers).
+__device__ inline uint32_t reserve_places(uint32_t nch, int bucket, uint32_t *__restrict__ counters) {
   constexpr int kWaves = kThreads / 64;
   __shared__ uint32_t s_wave[kWaves][kDepthBuckets], s_base[kDepthBuckets];
-  const int wave = threadIdx.x >> 6;
-  const uint32_t nch = vis ? (cnt + kSplatChunk - 1) / kSplatChunk : 0u;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t present = nch ? (1u << bucket) : 0u;  // buckets of this wave's visible cells
   for (int off = 32; off > 0; off >>= 1) present |= __shfl_xor(present, off, 64);
   uint32_t local = 0;
@@ -118,30 +103,100 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(const float *__restrict_
     s_base[threadIdx.x] = sum ? atomicAdd(&counters[4 + threadIdx.x], sum) : 0u;
   }
   __syncthreads();
+  uint32_t pos = 0;
   if (nch) {
-    uint32_t pos = s_base[bucket] + local;
+    pos = s_base[bucket] + local;
     for (int w = 0; w < wave; ++w) pos += s_wave[w][bucket];
-    for (uint32_t k = 0; k < nch; ++k) {
-      const uint32_t off = k * kSplatChunk;
-      chunks[(size_t)bucket * cap + pos + k] = make_uint2(start + off, min(kSplatChunk, cnt - off));
-    }
   }
+  return pos;
+}
+
+// Frame totals: work items, visible cells and their points, reduced per wave
+// with one atomic per wave.
+__device__ inline void add_totals(bool vis, uint32_t nch, uint32_t cnt, uint32_t *__restrict__ counters) {
   uint32_t wave_chunks = nch;
   for (int off = 32; off > 0; off >>= 1) wave_chunks += __shfl_xor(wave_chunks, off, 64);
   const uint64_t vis_mask = __ballot(vis);
   uint32_t pts = vis ? cnt : 0u;
   for (int off = 32; off > 0; off >>= 1) pts += __shfl_xor(pts, off, 64);
-  if (lane == 0 && wave_chunks) {
+  if ((threadIdx.x & 63) == 0 && wave_chunks) {
     atomicAdd(&counters[0], wave_chunks);
     atomicAdd(&counters[1], (uint32_t)__popcll(vis_mask));
     atomicAdd(reinterpret_cast<unsigned long long *>(&counters[2]), (unsigned long long)pts);
   }
 }
 
+// One lane per cell.  A visible non-empty cell is cut into splat work items
+// of at most kSplatChunk points, queued in the depth bucket of the cell's
+// centre.
+__global__ __launch_bounds__(kThreads) void cull_kernel(const float *__restrict__ aabb,
+                                                        const uint32_t *__restrict__ cell_start, uint32_t n_cells,
+                                                        CullParams prm, uint8_t *__restrict__ flags,
+                                                        uint2 *__restrict__ chunks, uint32_t cap,
+                                                        uint32_t *__restrict__ counters) {
+  const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
+  uint32_t start = 0, cnt = 0;
+  bool vis = false;
+  int bucket = 0;
+  if (c < n_cells) {
+    start = cell_start[c];
+    cnt = cell_start[c + 1] - start;
+    if (cnt > 0)
+      vis = cell_visible(prm, aabb[6ull * c + 0], aabb[6ull * c + 1], aabb[6ull * c + 2], aabb[6ull * c + 3],
+                         aabb[6ull * c + 4], aabb[6ull * c + 5], &bucket);
+    flags[c] = vis ? 1 : 0;
+  }
+  const uint32_t nch = vis ? (cnt + kSplatChunk - 1) / kSplatChunk : 0u;
+  const uint32_t pos = reserve_places(nch, bucket, counters);
+  for (uint32_t k = 0; k < nch; ++k) {
+    const uint32_t off = k * kSplatChunk;
+    chunks[(size_t)bucket * cap + pos + k] = make_uint2(start + off, min(kSplatChunk, cnt - off));
+  }
+  add_totals(vis, nch, cnt, counters);
+}
+
+// Several views at once: a cell is tested against every view's frustum, and
+// its work items carry the mask of the views that see it (bit v = view v) and
+// go to the queue of the nearest of those views' depth buckets.
+__global__ __launch_bounds__(kThreads) void cull_views_kernel(const float *__restrict__ aabb,
+                                                              const uint32_t *__restrict__ cell_start,
+                                                              uint32_t n_cells, ViewsCull prm,
+                                                              uint8_t *__restrict__ flags, uint4 *__restrict__ items,
+                                                              uint32_t cap, uint32_t *__restrict__ counters) {
+  const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
+  uint32_t start = 0, cnt = 0, mask = 0;
+  int bucket = kDepthBuckets - 1;
+  if (c < n_cells) {
+    start = cell_start[c];
+    cnt = cell_start[c + 1] - start;
+    if (cnt > 0) {
+      const double lo0 = aabb[6ull * c + 0], lo1 = aabb[6ull * c + 1], lo2 = aabb[6ull * c + 2];
+      const double hi0 = aabb[6ull * c + 3], hi1 = aabb[6ull * c + 4], hi2 = aabb[6ull * c + 5];
+      for (int v = 0; v < prm.n; ++v) {
+        int b = 0;
+        if (cell_visible(prm.v[v], lo0, lo1, lo2, hi0, hi1, hi2, &b)) {
+          mask |= 1u << v;
+          bucket = min(bucket, b);
+        }
+      }
+    }
+    flags[c] = mask ? 1 : 0;
+  }
+  const bool vis = mask != 0;
+  const uint32_t nch = vis ? (cnt + kSplatChunk - 1) / kSplatChunk : 0u;
+  const uint32_t pos = reserve_places(nch, bucket, counters);
+  for (uint32_t k = 0; k < nch; ++k) {
+    const uint32_t off = k * kSplatChunk;
+    items[(size_t)bucket * cap + pos + k] = make_uint4(start + off, min(kSplatChunk, cnt - off), mask, 0u);
+  }
+  add_totals(vis, nch, cnt, counters);
+}
+
 // Work item `i` of the frame, walking the depth-bucket queues nearest first
 // (counters[4 + b] items in bucket b); false past the last item.
-__device__ inline bool work_item(uint32_t i, const uint32_t *__restrict__ counters, const uint2 *__restrict__ chunks,
-                                 uint32_t cap, uint2 *ch) {
+template <typename Item>
+__device__ inline bool work_item(uint32_t i, const uint32_t *__restrict__ counters, const Item *__restrict__ chunks,
+                                 uint32_t cap, Item *ch) {
   if (i >= counters[0]) return false;
   for (int b = 0; b < kDepthBuckets; ++b) {
     const uint32_t nb = counters[4 + b];
@@ -190,59 +245,45 @@ __device__ inline uint32_t small_div(uint32_t p, float inv_w) {
   return (uint32_t)(((float)p + 0.5f) * inv_w);
 }
 
-// Project the work item's points (thread t takes points t, t + 256, ...):
-// kk = key, (px, py) = pixel, px = ~0u if the point is not drawn; and the
-// screen rectangle [x0, x1] x [y0, y1] of the drawn points over the whole
-// block (x0 > x1 if none).  Contains block barriers.
-__device__ inline void project_work_item(const float *__restrict__ xs, const float *__restrict__ ys,
-                                         const float *__restrict__ zs, uint2 ch, const SplatCam &cam,
-                                         uint64_t (&kk)[kPtsPerThread], uint32_t (&px)[kPtsPerThread],
-                                         uint32_t (&py)[kPtsPerThread], uint32_t *s_bb, uint32_t *rx0, uint32_t *ry0,
-                                         uint32_t *rx1, uint32_t *ry1) {
-  const int tid = threadIdx.x;
+// Point j at (x, y, z) through the camera: true if drawn, with its key
+// (depth bits << 32 | j) and pixel.
+__device__ inline bool project_point(float x, float y, float z, uint32_t j, const SplatCam &cam, uint64_t &k,
+                                     uint32_t &px, uint32_t &py) {
   const float *P = cam.P;
-  uint32_t x0 = ~0u, y0 = ~0u, x1 = 0, y1 = 0;
-#pragma unroll
-  for (int q = 0; q < kPtsPerThread; ++q) {
-    const uint32_t i = tid + q * kThreads;
-    px[q] = ~0u;
-    py[q] = 0;
-    kk[q] = 0;
-    if (i < ch.y) {
-      const uint32_t j = ch.x + i;
-      const float x = xs[j], y = ys[j], z = zs[j];
-      const float a = ((P[0] * x + P[1] * y) + P[2] * z) + P[3];
-      const float b = ((P[4] * x + P[5] * y) + P[6] * z) + P[7];
-      const float w = ((P[8] * x + P[9] * y) + P[10] * z) + P[11];
-      if (w >= cam.z_near && w <= cam.z_far) {
-        const float u = a / w;
-        const float v = b / w;
-        if (u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf) {
-          px[q] = (uint32_t)u;
-          py[q] = (uint32_t)v;
-          kk[q] = ((uint64_t)__float_as_uint(w) << 32) | j;
-          x0 = min(x0, px[q]);
-          x1 = max(x1, px[q]);
-          y0 = min(y0, py[q]);
-          y1 = max(y1, py[q]);
-        }
-      }
+  const float a = ((P[0] * x + P[1] * y) + P[2] * z) + P[3];
+  const float b = ((P[4] * x + P[5] * y) + P[6] * z) + P[7];
+  const float w = ((P[8] * x + P[9] * y) + P[10] * z) + P[11];
+  if (w >= cam.z_near && w <= cam.z_far) {
+    const float u = a / w;
+    const float v = b / w;
+    if (u >= 0.f && u < cam.Wf && v >= 0.f && v < cam.Hf) {
+      px = (uint32_t)u;
+      py = (uint32_t)v;
+      k = ((uint64_t)__float_as_uint(w) << 32) | j;
+      return true;
     }
   }
+  return false;
+}
+
+// The block-wide rectangle of the lanes' rectangles [x0, x1] x [y0, y1]
+// (x0 > x1 if none).  Contains block barriers.
+__device__ inline void block_rect(uint32_t x0, uint32_t y0, uint32_t x1, uint32_t y1, uint32_t *s_bb, uint32_t *rx0,
+                                  uint32_t *ry0, uint32_t *rx1, uint32_t *ry1) {
   for (int off = 32; off > 0; off >>= 1) {
     x0 = min(x0, (uint32_t)__shfl_xor(x0, off, 64));
     y0 = min(y0, (uint32_t)__shfl_xor(y0, off, 64));
     x1 = max(x1, (uint32_t)__shfl_xor(x1, off, 64));
     y1 = max(y1, (uint32_t)__shfl_xor(y1, off, 64));
   }
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     s_bb[0] = ~0u;
     s_bb[1] = ~0u;
     s_bb[2] = 0;
     s_bb[3] = 0;
   }
   __syncthreads();
-  if ((tid & 63) == 0) {
+  if ((threadIdx.x & 63) == 0) {
     atomicMin(&s_bb[0], x0);
     atomicMin(&s_bb[1], y0);
     atomicMax(&s_bb[2], x1);
@@ -255,22 +296,50 @@ __device__ inline void project_work_item(const float *__restrict__ xs, const flo
   *ry1 = s_bb[3];
 }
 
-template <bool COUNT>
-__global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
-                                                         const float *__restrict__ zs, const uint2 *__restrict__ chunks,
-                                                         uint32_t cap, uint32_t *__restrict__ counters,
-                                                         SplatCam cam, uint64_t *__restrict__ key) {
-  __shared__ unsigned long long zb[kDedupPx];
-  __shared__ uint32_t s_bb[4];
-  uint2 ch;
-  if (!work_item(blockIdx.x, counters, chunks, cap, &ch)) return;
+// Project the work item's points (thread t takes points t, t + 256, ...):
+// kk = key, (px, py) = pixel, px = ~0u if the point is not drawn; and the
+// screen rectangle [x0, x1] x [y0, y1] of the drawn points over the whole
+// block (x0 > x1 if none).  Contains block barriers.
+__device__ inline void project_work_item(const float *__restrict__ xs, const float *__restrict__ ys,
+                                         const float *__restrict__ zs, uint2 ch, const SplatCam &cam,
+                                         uint64_t (&kk)[kPtsPerThread], uint32_t (&px)[kPtsPerThread],
+                                         uint32_t (&py)[kPtsPerThread], uint32_t *s_bb, uint32_t *rx0, uint32_t *ry0,
+                                         uint32_t *rx1, uint32_t *ry1) {
   const int tid = threadIdx.x;
-  uint32_t issued = 0;
-  uint64_t kk[kPtsPerThread];
-  uint32_t px[kPtsPerThread], py[kPtsPerThread];
-  uint32_t x0, y0, x1, y1;
-  project_work_item(xs, ys, zs, ch, cam, kk, px, py, s_bb, &x0, &y0, &x1, &y1);
-  if (x0 > x1) return;  // nothing drawn (the same for the whole block)
+  uint32_t x0 = ~0u, y0 = ~0u, x1 = 0, y1 = 0;
+#pragma unroll
+  for (int q = 0; q < kPtsPerThread; ++q) {
+    const uint32_t i = tid + q * kThreads;
+    uint64_t k = 0;
+    uint32_t ux = ~0u, uy = 0;
+    if (i < ch.y) {
+      const uint32_t j = ch.x + i;
+      if (project_point(xs[j], ys[j], zs[j], j, cam, k, ux, uy)) {
+        x0 = min(x0, ux);
+        x1 = max(x1, ux);
+        y0 = min(y0, uy);
+        y1 = max(y1, uy);
+      } else {
+        ux = ~0u;
+      }
+    }
+    kk[q] = k;
+    px[q] = ux;
+    py[q] = uy;
+  }
+  block_rect(x0, y0, x1, y1, s_bb, rx0, ry0, rx1, ry1);
+}
+
+// Lower the global z-buffer (row length W) by the block's projected points,
+// whose rectangle [x0, x1] x [y0, y1] is not empty: through the LDS z-buffer
+// zb over the rectangle when it has at most kDedupPx pixels, else point by
+// point.  Contains block barriers.
+template <bool COUNT>
+__device__ inline void splat_block(const uint64_t (&kk)[kPtsPerThread], const uint32_t (&px)[kPtsPerThread],
+                                   const uint32_t (&py)[kPtsPerThread], uint32_t x0, uint32_t y0, uint32_t x1,
+                                   uint32_t y1, uint32_t W, uint64_t *__restrict__ key, unsigned long long *zb,
+                                   uint32_t &issued) {
+  const int tid = threadIdx.x;
   const uint32_t bw = x1 - x0 + 1;
   const uint64_t a64 = (uint64_t)bw * (uint64_t)(y1 - y0 + 1);
   if (a64 <= (uint64_t)kDedupPx) {
@@ -286,16 +355,89 @@ __global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict
       const uint64_t k = zb[p];
       if (k == ~0ull) continue;
       const uint32_t ry = small_div(p, inv_bw), rx = p - ry * bw;
-      global_min<COUNT>(key + (size_t)(y0 + ry) * cam.W + (x0 + rx), k, issued);
+      global_min<COUNT>(key + (size_t)(y0 + ry) * W + (x0 + rx), k, issued);
     }
   } else {
 #pragma unroll
     for (int q = 0; q < kPtsPerThread; ++q)
-      if (px[q] != ~0u) global_min<COUNT>(key + (size_t)py[q] * cam.W + px[q], kk[q], issued);
+      if (px[q] != ~0u) global_min<COUNT>(key + (size_t)py[q] * W + px[q], kk[q], issued);
   }
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kThreads) void splat_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
+                                                         const float *__restrict__ zs, const uint2 *__restrict__ chunks,
+                                                         uint32_t cap, uint32_t *__restrict__ counters,
+                                                         SplatCam cam, uint64_t *__restrict__ key) {
+  __shared__ unsigned long long zb[kDedupPx];
+  __shared__ uint32_t s_bb[4];
+  uint2 ch;
+  if (!work_item(blockIdx.x, counters, chunks, cap, &ch)) return;
+  uint32_t issued = 0;
+  uint64_t kk[kPtsPerThread];
+  uint32_t px[kPtsPerThread], py[kPtsPerThread];
+  uint32_t x0, y0, x1, y1;
+  project_work_item(xs, ys, zs, ch, cam, kk, px, py, s_bb, &x0, &y0, &x1, &y1);
+  if (x0 > x1) return;  // nothing drawn (the same for the whole block)
+  splat_block<COUNT>(kk, px, py, x0, y0, x1, y1, cam.W, key, zb, issued);
   if constexpr (COUNT) {
     for (int off = 32; off > 0; off >>= 1) issued += __shfl_xor(issued, off, 64);
-    if ((tid & 63) == 0 && issued) atomicAdd(&counters[kAtomicWord], issued);
+    if ((threadIdx.x & 63) == 0 && issued) atomicAdd(&counters[kAtomicWord], issued);
+  }
+}
+
+// Several views at once: the work item's points are read from memory once,
+// kept in registers, and projected and splatted into each view of its mask
+// in turn, as splat_kernel does for one view.
+__global__ __launch_bounds__(kThreads) void splat_views_kernel(const float *__restrict__ xs,
+                                                               const float *__restrict__ ys,
+                                                               const float *__restrict__ zs,
+                                                               const uint4 *__restrict__ items, uint32_t cap,
+                                                               const uint32_t *__restrict__ counters, ViewsSplat vs) {
+  __shared__ unsigned long long zb[kDedupPx];
+  __shared__ uint32_t s_bb[4];
+  uint4 it;
+  if (!work_item(blockIdx.x, counters, items, cap, &it)) return;
+  const int tid = threadIdx.x;
+  float x[kPtsPerThread], y[kPtsPerThread], z[kPtsPerThread];
+#pragma unroll
+  for (int q = 0; q < kPtsPerThread; ++q) {
+    const uint32_t i = tid + q * kThreads;
+    x[q] = y[q] = z[q] = 0.f;
+    if (i < it.y) {
+      x[q] = xs[it.x + i];
+      y[q] = ys[it.x + i];
+      z[q] = zs[it.x + i];
+    }
+  }
+  uint32_t issued = 0;
+  // the mask is the same for every lane: keep it (and the view index) scalar
+  for (uint32_t m = __builtin_amdgcn_readfirstlane(it.z); m; m &= m - 1) {
+    const int v = __builtin_ctz(m);
+    const SplatCam &cam = vs.cam[v];
+    uint64_t kk[kPtsPerThread];
+    uint32_t px[kPtsPerThread], py[kPtsPerThread];
+    uint32_t x0 = ~0u, y0 = ~0u, x1 = 0, y1 = 0;
+#pragma unroll
+    for (int q = 0; q < kPtsPerThread; ++q) {
+      const uint32_t i = tid + q * kThreads;
+      uint64_t k = 0;
+      uint32_t ux = ~0u, uy = 0;
+      if (i < it.y && project_point(x[q], y[q], z[q], it.x + i, cam, k, ux, uy)) {
+        x0 = min(x0, ux);
+        x1 = max(x1, ux);
+        y0 = min(y0, uy);
+        y1 = max(y1, uy);
+      } else {
+        ux = ~0u;
+      }
+      kk[q] = k;
+      px[q] = ux;
+      py[q] = uy;
+    }
+    block_rect(x0, y0, x1, y1, s_bb, &x0, &y0, &x1, &y1);
+    if (x0 <= x1) splat_block<false>(kk, px, py, x0, y0, x1, y1, cam.W, vs.key[v], zb, issued);
+    __syncthreads();  // s_bb and zb are reused by the next view
   }
 }
 
@@ -837,6 +979,23 @@ hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counte
     splat_kernel<true><<<g, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, cap, counters, cam, key);
   else
     splat_kernel<false><<<g, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, cap, counters, cam, key);
+  return hipGetLastError();
+}
+
+hipError_t launch_cull_views(const CloudDev &c, const ViewsCull &prm, uint8_t *flags, uint4 *items, uint32_t *counters,
+                             hipStream_t s) {
+  if (prm.n < 1 || prm.n > kViewsPerPass) return hipErrorInvalidValue;
+  const uint32_t nb = (c.n_cells + kThreads - 1) / kThreads;
+  cull_views_kernel<<<nb, kThreads, 0, s>>>(c.aabb, c.cell_start, c.n_cells, prm, flags, items, c.max_chunks,
+                                            counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_splat_views(const CloudDev &c, const uint4 *items, const uint32_t *counters, const ViewsSplat &vs,
+                              hipStream_t s) {
+  if (vs.n < 1 || vs.n > kViewsPerPass) return hipErrorInvalidValue;
+  if (c.max_chunks == 0) return hipSuccess;
+  splat_views_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, items, c.max_chunks, counters, vs);
   return hipGetLastError();
 }
 

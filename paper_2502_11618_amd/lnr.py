@@ -111,6 +111,8 @@ def _load():
         "lnr_render": (i32, [vp, vp, ctypes.POINTER(lnr_camera), ctypes.POINTER(lnr_image), ctypes.c_uint32, vp]),
         "lnr_render_soft": (i32, [vp, vp, ctypes.POINTER(lnr_camera), ctypes.POINTER(lnr_image), f32, ctypes.c_uint32,
                                   vp]),
+        "lnr_render_views": (i32, [vp, vp, ctypes.POINTER(lnr_camera), ctypes.POINTER(lnr_image), i32,
+                                   ctypes.c_uint32, vp]),
         "lnr_render_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), vp]),
         "lnr_render_atomic_count": (i32, [vp, ctypes.POINTER(u64)]),
         "lnr_measure_atomic_min": (i32, [vp, u64, i32, u64, vp, ctypes.POINTER(ctypes.c_double),
@@ -314,6 +316,15 @@ def lnr_render_soft(ctx: Context, cloud: Cloud, cam, image: Image, soft_eps: flo
     img = image.struct()
     _check(_lib.lnr_render_soft(ctx.handle, cloud.handle, ctypes.byref(c), ctypes.byref(img), float(soft_eps), flags,
                                 _stream(stream)), ctx.handle)
+
+
+def lnr_render_views(ctx: Context, cloud: Cloud, cams, images, flags: int = 0, stream=None) -> None:
+    """Several views in one pass over the cloud; cams and images are sequences
+    of equal length (images[v] receives what lnr_render of cams[v] writes)."""
+    n = len(cams)
+    c_arr = (lnr_camera * max(n, 1))(*[c if isinstance(c, lnr_camera) else camera_struct(c) for c in cams])
+    i_arr = (lnr_image * max(len(images), 1))(*[im.struct() for im in images])
+    _check(_lib.lnr_render_views(ctx.handle, cloud.handle, c_arr, i_arr, n, flags, _stream(stream)), ctx.handle)
 
 
 def lnr_render_stats(ctx: Context, n_cells: Optional[int] = None):

@@ -156,3 +156,24 @@ def test_unknown_precision_is_rejected(lnr, ctx):
         assert e.value.status == lnr.LNR_E_INVALID_ARG
     for prec in (lnr.LNR_FP8_E4M3, lnr.LNR_FP8_E4M3X3):
         lnr.lnr_unet_destroy(lnr.lnr_unet_load(ctx, blob, prec))
+
+
+def test_render_views_leaves_outputs_untouched(lnr, room_cloud, room_cams):
+    """Each allocation of a multi-view render in turn fails: no image is
+    written, and the scratch left equals a clean run's."""
+    cams = list(room_cams[:10])
+    clean = lnr.lnr_context_create(0)
+    lnr.lnr_render_views(clean, room_cloud, cams, [lnr.Image(c.height, c.width) for c in cams])
+    lnr.lnr_sync(clean)
+    scratch = lnr.lnr_allocated_bytes(clean)
+    ctx = lnr.lnr_context_create(0)
+    imgs = [_sentinel_image(lnr, c.height, c.width) for c in cams]
+    fails = 0
+    for _ in _sweep(lnr, ctx, lambda: lnr.lnr_render_views(ctx, room_cloud, cams, imgs)):
+        assert all(_untouched(i) for i in imgs), "a failed multi-view render wrote an image"
+        fails += 1
+    # cull flags, work items and counters; the grow-only scratch keeps what
+    # an attempt allocated before its failure, so the third attempt succeeds
+    assert fails >= 2
+    lnr.lnr_sync(ctx)
+    assert lnr.lnr_allocated_bytes(ctx) == scratch
