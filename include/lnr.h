@@ -309,16 +309,19 @@ lnr_status lnr_profile_read(lnr_context *ctx, lnr_kernel_time *out, int32_t max,
 /* ---------------------------------------------------------------------------
  * Serving: many viewer sessions rendering the same resident cloud.
  *
- * Sessions are opened with their resolution; a session's image and output
- * buffers are allocated from the context's budget when it opens, so a session
- * that does not fit is refused with LNR_E_BUDGET (admission by HBM budget).
+ * Sessions are opened with their resolution; a session's two output planes
+ * are allocated from the context's budget when it opens, so a session that
+ * does not fit is refused with LNR_E_BUDGET (admission by HBM budget).
  * Each submitted camera becomes a request.  lnr_server_step takes a free lane
- * (a HIP stream with its own scratch) and the oldest pending request, joins it
- * with up to max_batch - 1 other pending requests of the same resolution, and
- * enqueues for them: render (or soft render), depth filter, and one batched
- * U-Net over all of them (each convolution processes the whole batch in one
- * launch; the launch sequence of every (resolution, batch size) is captured
- * once as a HIP graph and replayed).  Lanes run concurrently, so batches
+ * (a HIP stream with its own scratch and an RGBDA image per batch slot) and
+ * the oldest pending request, joins it with up to max_batch - 1 other pending
+ * requests of the same resolution, and enqueues for them: render (or soft
+ * render), depth filter and input pack per request, and one batched U-Net
+ * over all of them (each convolution processes the whole batch in one
+ * launch).  With use_graphs, the whole launch sequence of every (resolution,
+ * batch size) is captured once as a HIP graph and replayed: the kernels read
+ * the batch's cameras and output pointers from device arrays that each step
+ * writes before the replay.  Lanes run concurrently, so batches
  * overlap on the device.  A session has at most one request in flight; a
  * newer camera submitted while the older one is still pending replaces it
  * (the older is reported as superseded).  Every image is computed exactly as
@@ -333,7 +336,7 @@ typedef struct {
   float filter_strength;    /* depth filter strength                                */
   int32_t soft;             /* non-zero: soft z-buffer with soft_eps                */
   float soft_eps;
-  int32_t use_graphs;       /* non-zero: replay captured HIP graphs for the U-Net   */
+  int32_t use_graphs;       /* non-zero: replay a captured HIP graph per batch      */
   int32_t max_width, max_height; /* largest session resolution (sizes lane scratch) */
 } lnr_server_config;
 typedef struct {

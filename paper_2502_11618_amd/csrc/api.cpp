@@ -740,8 +740,13 @@ static lnr_status check_target(lnr_context *ctx, const lnr_camera *cam, const ln
   return LNR_OK;
 }
 
+// dev (may be nullptr): the same camera in device memory; the culling and
+// projection kernels then read it there (the tiled and soft splats only), so
+// the launches can be captured once and replayed for other cameras of the
+// same size
 static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c, const lnr_camera *cam,
-                              lnr_image *out, uint32_t flags, bool soft, float soft_eps, void *hip_stream) {
+                              lnr_image *out, uint32_t flags, bool soft, float soft_eps, void *hip_stream,
+                              const DevCam *dev = nullptr) {
   if (!ctx) return LNR_E_INVALID_ARG;
   if (soft && !(std::isfinite(soft_eps) && soft_eps >= 0.f))
     return fail(ctx, LNR_E_INVALID_ARG, "soft_eps must be finite and >= 0");
@@ -769,9 +774,11 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   if (!atomic && (st = ensure_tiled(ctx, scr, tg, c->d.n)) != LNR_OK) return st;
   if (soft && (st = ensure(ctx, scr.soft_acc, 16ull * npix)) != LNR_OK) return st;
   const TiledSplatBufs tb = tiled_bufs(scr);
+  if (dev && atomic) return fail(ctx, LNR_E_INVALID_ARG, "a camera in device memory needs the tiled splat");
   LNR_LAUNCH(ctx, "clear", s, launch_clear(out->key, npix, counters, tb.tile_nseg, atomic ? 0u : tg.n_tiles, s));
-  LNR_LAUNCH(ctx, "cull", s, launch_cull(c->d, prm, static_cast<uint8_t *>(scr.flags.p), static_cast<uint2 *>(scr.chunks.p),
-                           counters, s));
+  LNR_LAUNCH(ctx, "cull", s,
+             launch_cull(c->d, prm, dev ? &dev->cull : nullptr, static_cast<uint8_t *>(scr.flags.p),
+                         static_cast<uint2 *>(scr.chunks.p), counters, s));
   const uint2 *chunks = static_cast<const uint2 *>(scr.chunks.p);
   uint32_t *rgba32 = reinterpret_cast<uint32_t *>(out->rgba);
   if (atomic) {
@@ -781,12 +788,12 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
     static const char *const names[5] = {"bin", "tilescan", "segsort", "tile", "tileres"};
     for (int stage = 0; stage < 5; ++stage)
       LNR_LAUNCH(ctx, names[stage], s,
-                 launch_tiled_splat(c->d, chunks, counters, sc, (uint32_t)cam->height, tb, out->key, out->depth,
-                                    rgba32, stage, s));
+                 launch_tiled_splat(c->d, chunks, counters, sc, dev ? &dev->splat : nullptr, (uint32_t)cam->height,
+                                    tb, out->key, out->depth, rgba32, stage, s));
   }
   if (soft)
     LNR_LAUNCH(ctx, "soft", s,
-               launch_soft(c->d, chunks, counters, sc, out->key, 1.0f + soft_eps,
+               launch_soft(c->d, chunks, counters, sc, dev ? &dev->splat : nullptr, out->key, 1.0f + soft_eps,
                            static_cast<uint32_t *>(scr.soft_acc.p), out->depth, rgba32, npix, s));
   ctx->last_stream = s;
   ctx->rendered = true;
@@ -1312,9 +1319,6 @@ struct ServerSession {
   int W = 0, H = 0;
   void *buf = nullptr;
   size_t bytes = 0;
-  uint64_t *key = nullptr;
-  float *depth = nullptr;
-  uint8_t *rgba = nullptr;
   float *out[2] = {nullptr, nullptr};
   int next_out = 0;
   bool pending = false;
@@ -1334,6 +1338,14 @@ struct ServerLane {
   std::vector<const float *> outs;
   float **head_outs_dev = nullptr;   // device array [max_batch]
   float **head_outs_host = nullptr;  // pinned host staging of the same
+  DevCam *cams_dev = nullptr;        // the batch's cameras, device array [max_batch]
+  DevCam *cams_host = nullptr;       // pinned host staging of the same
+  // the RGBDA image of each batch slot (rendered, filtered, packed), at the
+  // largest session size: a key plane, a depth plane and an rgba plane of
+  // max_batch slots each, slot b at pixel b * slot_px of every plane
+  void *slot_buf = nullptr;
+  size_t slot_bytes = 0, slot_px = 0;
+  // one graph per (height, width, batch): every launch of a whole batch
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_defs;
 };
@@ -1365,6 +1377,9 @@ void server_release(lnr_server *srv) {
       dfree(ctx, b->p, b->cap);
     if (l.head_outs_dev) dfree(ctx, l.head_outs_dev, 8ull * 16);
     if (l.head_outs_host) (void)hipHostFree(l.head_outs_host);
+    if (l.cams_dev) dfree(ctx, l.cams_dev, sizeof(DevCam) * 16);
+    if (l.cams_host) (void)hipHostFree(l.cams_host);
+    if (l.slot_buf) dfree(ctx, l.slot_buf, l.slot_bytes);
     if (l.ev_start) (void)hipEventDestroy(l.ev_start);
     if (l.ev_done) (void)hipEventDestroy(l.ev_done);
     if (l.stream) (void)hipStreamDestroy(l.stream);
@@ -1441,11 +1456,16 @@ lnr_status lnr_server_create(lnr_context *ctx, const lnr_cloud *c, const lnr_une
     }
   }
   const size_t act = unet_layout(u, mH, mW, cfg->max_batch).bytes;
+  // per batch slot: key (8 B), depth (4 B) and rgba (4 B) per pixel, each
+  // plane of every slot 256-byte aligned
+  const size_t slot_px = (npix + 31) / 32 * 32;
+  const size_t slot_bytes = 16 * slot_px * (size_t)cfg->max_batch;
   for (auto &l : srv->lanes) {
     hipError_t e = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&l.ev_start);
     if (e == hipSuccess) e = hipEventCreate(&l.ev_done);
     if (e == hipSuccess) e = hipHostMalloc((void **)&l.head_outs_host, 8ull * 16, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&l.cams_host, sizeof(DevCam) * 16, hipHostMallocDefault);
     if (e != hipSuccess) {
       server_release(srv.get());
       return hip_fail(ctx, e, "server lane setup");
@@ -1456,10 +1476,14 @@ lnr_status lnr_server_create(lnr_context *ctx, const lnr_cloud *c, const lnr_une
         (st = ensure(ctx, l.sc.act, act)) != LNR_OK ||
         (st = ensure_tiled(ctx, l.sc, tiled_splat_grid((uint32_t)mW, (uint32_t)mH, c->d.n), c->d.n)) != LNR_OK ||
         (cfg->soft && (st = ensure(ctx, l.sc.soft_acc, 16 * npix)) != LNR_OK) ||
-        (st = dalloc(ctx, (void **)&l.head_outs_dev, 8ull * 16)) != LNR_OK) {
+        (st = dalloc(ctx, (void **)&l.head_outs_dev, 8ull * 16)) != LNR_OK ||
+        (st = dalloc(ctx, (void **)&l.cams_dev, sizeof(DevCam) * 16)) != LNR_OK ||
+        (st = dalloc(ctx, &l.slot_buf, slot_bytes)) != LNR_OK) {
       server_release(srv.get());
       return st;
     }
+    l.slot_bytes = slot_bytes;
+    l.slot_px = slot_px;
   }
   ++ctx->children;
   *out = srv.release();
@@ -1494,17 +1518,11 @@ lnr_status lnr_server_open_session(lnr_server *srv, int32_t width, int32_t heigh
   if (st != LNR_OK) return st;
   const size_t np = (size_t)width * height;
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t bytes = al(8 * np) + al(4 * np) + al(4 * np) + 2 * al(12 * np);
+  const size_t bytes = 2 * al(12 * np);  // two output planes; the images live in the lanes' slots
   ServerSession ss;
   if ((st = dalloc(ctx, &ss.buf, bytes)) != LNR_OK) return st;  // LNR_E_BUDGET: not admitted
   ss.bytes = bytes;
   char *p = static_cast<char *>(ss.buf);
-  ss.key = reinterpret_cast<uint64_t *>(p);
-  p += al(8 * np);
-  ss.depth = reinterpret_cast<float *>(p);
-  p += al(4 * np);
-  ss.rgba = reinterpret_cast<uint8_t *>(p);
-  p += al(4 * np);
   ss.out[0] = reinterpret_cast<float *>(p);
   p += al(12 * np);
   ss.out[1] = reinterpret_cast<float *>(p);
@@ -1616,23 +1634,43 @@ lnr_status lnr_server_step(lnr_server *srv, int32_t *launched) {
     }
   } rb{srv, lane, batch, ctx->profiling, {}};
   ctx->profiling = false;
-  LNR_HIP(ctx, hipEventRecord(lane->ev_start, s));
   const UNetLayout lay = unet_layout(srv->unet, H, W, B);
   for (int b = 0; b < B; ++b) {
     ServerSession &ss = srv->sessions[batch[b]];
-    lnr_image img{ss.key, ss.depth, ss.rgba, ss.W, ss.H};
-    st = render_impl(ctx, lane->sc, srv->cloud, &ss.cam, &img, 0, srv->cfg.soft != 0, srv->cfg.soft_eps, s);
-    if (st == LNR_OK && srv->cfg.n_levels > 0)
-      st = depth_filter_impl(ctx, lane->sc, &img, srv->cfg.n_levels, srv->cfg.filter_strength, s);
-    if (st == LNR_OK) st = unet_pack(ctx, lane->sc, srv->unet, lay, b, ss.depth, reinterpret_cast<const uint32_t *>(ss.rgba), s);
-    if (st != LNR_OK) return st;
+    lane->cams_host[b].cull = make_cull_params(&ss.cam, false);
+    lane->cams_host[b].splat = make_splat_cam(&ss.cam);
     float *o = ss.out[ss.next_out];
     ss.next_out ^= 1;
     rb.toggled.push_back(batch[b]);
     lane->head_outs_host[b] = o;
     lane->outs.push_back(o);
   }
+  // Every launch of the batch: per slot render (camera read from cams_dev),
+  // depth filter and input pack, then the batched U-Net writing through
+  // head_outs_dev.  Nothing in it depends on the batch's cameras or sessions
+  // beyond those two device arrays, so one capture per (size, batch) serves
+  // every later batch of that shape.
+  char *slots = static_cast<char *>(lane->slot_buf);
+  const size_t sp = lane->slot_px, mb = (size_t)srv->cfg.max_batch;
+  auto enqueue = [&]() -> lnr_status {
+    for (int b = 0; b < B; ++b) {
+      const ServerSession &ss = srv->sessions[batch[b]];
+      lnr_image img{reinterpret_cast<uint64_t *>(slots) + (size_t)b * sp,
+                    reinterpret_cast<float *>(slots + 8 * sp * mb) + (size_t)b * sp,
+                    reinterpret_cast<uint8_t *>(slots + 12 * sp * mb) + 4 * (size_t)b * sp, W, H};
+      lnr_status r = render_impl(ctx, lane->sc, srv->cloud, &ss.cam, &img, 0, srv->cfg.soft != 0,
+                                 srv->cfg.soft_eps, s, lane->cams_dev + b);
+      if (r == LNR_OK && srv->cfg.n_levels > 0)
+        r = depth_filter_impl(ctx, lane->sc, &img, srv->cfg.n_levels, srv->cfg.filter_strength, s);
+      if (r == LNR_OK)
+        r = unet_pack(ctx, lane->sc, srv->unet, lay, b, img.depth, reinterpret_cast<const uint32_t *>(img.rgba), s);
+      if (r != LNR_OK) return r;
+    }
+    return unet_convs(ctx, lane->sc, srv->unet, lay, nullptr, lane->head_outs_dev, s);
+  };
+  LNR_HIP(ctx, hipEventRecord(lane->ev_start, s));
   LNR_HIP(ctx, hipMemcpyAsync(lane->head_outs_dev, lane->head_outs_host, 8ull * B, hipMemcpyHostToDevice, s));
+  LNR_HIP(ctx, hipMemcpyAsync(lane->cams_dev, lane->cams_host, sizeof(DevCam) * B, hipMemcpyHostToDevice, s));
   if (srv->cfg.use_graphs) {
     const auto key = std::make_tuple(H, W, B);
     auto it = lane->graphs.find(key);
@@ -1640,7 +1678,7 @@ lnr_status lnr_server_step(lnr_server *srv, int32_t *launched) {
       hipGraph_t g = nullptr;
       hipGraphExec_t ge = nullptr;
       LNR_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      st = unet_convs(ctx, lane->sc, srv->unet, lay, nullptr, lane->head_outs_dev, s);
+      st = enqueue();
       hipError_t e = hipStreamEndCapture(s, &g);
       if (st != LNR_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -1657,8 +1695,7 @@ lnr_status lnr_server_step(lnr_server *srv, int32_t *launched) {
     }
     LNR_HIP(ctx, hipGraphLaunch(it->second, s));
   } else {
-    st = unet_convs(ctx, lane->sc, srv->unet, lay, nullptr, lane->head_outs_dev, s);
-    if (st != LNR_OK) return st;
+    if ((st = enqueue()) != LNR_OK) return st;
   }
   LNR_HIP(ctx, hipEventRecord(lane->ev_done, s));
   rb.armed = false;

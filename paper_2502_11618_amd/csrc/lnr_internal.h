@@ -57,6 +57,13 @@ struct SplatCam {
   uint32_t W;
 };
 
+// A camera in device memory (serving: one per batch slot, rewritten before
+// each replay of a captured frame graph).
+struct DevCam {
+  CullParams cull;
+  SplatCam splat;
+};
+
 // Multi-view render: views per pass over the cloud.  The per-view cameras
 // travel as kernel arguments (a pass's culling parameters take 2.8 KB).
 constexpr int kViewsPerPass = 8;
@@ -130,11 +137,13 @@ struct TiledSplatBufs {
   uint32_t *tile_units;
   uint2 *units;
 };
+// cam_dev / prm_dev (may be nullptr): the same camera in device memory, read by
+// the kernels instead of the by-value copy (graph replays with new cameras)
 hipError_t launch_tiled_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counters, const SplatCam &cam,
-                              uint32_t H, const TiledSplatBufs &b, uint64_t *key, float *depth, uint32_t *rgba,
-                              int stage, hipStream_t s);
-hipError_t launch_cull(const CloudDev &c, const CullParams &prm, uint8_t *flags, uint2 *chunks, uint32_t *counters,
-                       hipStream_t s);
+                              const SplatCam *cam_dev, uint32_t H, const TiledSplatBufs &b, uint64_t *key,
+                              float *depth, uint32_t *rgba, int stage, hipStream_t s);
+hipError_t launch_cull(const CloudDev &c, const CullParams &prm, const CullParams *prm_dev, uint8_t *flags,
+                       uint2 *chunks, uint32_t *counters, hipStream_t s);
 // the atomic splat (global z-buffer); count_atomics: also add the number of
 // z-buffer atomics issued to counters[kAtomicWord]
 hipError_t launch_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counters, const SplatCam &cam,
@@ -156,8 +165,8 @@ hipError_t launch_resolve(const uint64_t *key, const uint32_t *rgbx, float *dept
                           hipStream_t s);
 // soft z-buffer: clear the colour sums, accumulate, resolve (acc = 4 x u32 per pixel)
 hipError_t launch_soft(const CloudDev &c, const uint2 *chunks, const uint32_t *counters, const SplatCam &cam,
-                       const uint64_t *key, float one_plus_eps, uint32_t *acc, float *depth, uint32_t *rgba,
-                       uint32_t npix, hipStream_t s);
+                       const SplatCam *cam_dev, const uint64_t *key, float one_plus_eps, uint32_t *acc, float *depth,
+                       uint32_t *rgba, uint32_t npix, hipStream_t s);
 
 // filter.hip
 hipError_t launch_pyramid(const float *depth, const uint32_t *rgba, int H, int W, int n, float *const *levels,

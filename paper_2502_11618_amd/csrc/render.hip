@@ -128,12 +128,16 @@ __device__ inline void add_totals(bool vis, uint32_t nch, uint32_t cnt, uint32_t
 
 // One lane per cell.  A visible non-empty cell is cut into splat work items
 // of at most kSplatChunk points, queued in the depth bucket of the cell's
-// centre.
+// centre.  DEV: the camera's parameters are read from device memory (prm_dev)
+// instead of the kernel arguments, so that a captured graph can be replayed
+// for new cameras.
+template <bool DEV>
 __global__ __launch_bounds__(kThreads) void cull_kernel(const float *__restrict__ aabb,
                                                         const uint32_t *__restrict__ cell_start, uint32_t n_cells,
-                                                        CullParams prm, uint8_t *__restrict__ flags,
-                                                        uint2 *__restrict__ chunks, uint32_t cap,
-                                                        uint32_t *__restrict__ counters) {
+                                                        CullParams prm_val, const CullParams *__restrict__ prm_dev,
+                                                        uint8_t *__restrict__ flags, uint2 *__restrict__ chunks,
+                                                        uint32_t cap, uint32_t *__restrict__ counters) {
+  const CullParams &prm = DEV ? *prm_dev : prm_val;
   const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
   uint32_t start = 0, cnt = 0;
   bool vis = false;
@@ -501,11 +505,14 @@ struct TileGrid {
   uint32_t tiles_x, tiles_y, n_tiles;
 };
 
+template <bool DEV>  // DEV: the camera comes from device memory (cam_dev), as in cull_kernel
 __global__ __launch_bounds__(kThreads) void bin_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
                                                        const float *__restrict__ zs, const uint2 *__restrict__ chunks,
-                                                       uint32_t cap, uint32_t *__restrict__ counters, SplatCam cam,
-                                                       TileGrid tg, uint64_t *__restrict__ recs,
-                                                       uint4 *__restrict__ segs, uint32_t *__restrict__ tile_nseg) {
+                                                       uint32_t cap, uint32_t *__restrict__ counters, SplatCam cam_val,
+                                                       const SplatCam *__restrict__ cam_dev, TileGrid tg,
+                                                       uint64_t *__restrict__ recs, uint4 *__restrict__ segs,
+                                                       uint32_t *__restrict__ tile_nseg) {
+  const SplatCam &cam = DEV ? *cam_dev : cam_val;
   // The work item's entries live in LDS, one u64 per slot (~0 = none).  With
   // the on-chip z-buffer, slot = pixel of the rectangle (row order) and the
   // entry its nearest key (depth bits << 32 | point index); otherwise slot =
@@ -832,13 +839,16 @@ __global__ __launch_bounds__(kThreads) void atomic_probe_kernel(uint64_t *__rest
 // depths are averaged).  A second pass over the same work items adds the colour
 // of every point whose depth is within (1 + eps) of its pixel's nearest depth
 // into integer sums; integer atomics make the result order independent.
+template <bool DEV>  // DEV: the camera comes from device memory (cam_dev), as in cull_kernel
 __global__ __launch_bounds__(kThreads) void soft_accum_kernel(const float *__restrict__ xs, const float *__restrict__ ys,
                                                               const float *__restrict__ zs,
                                                               const uint32_t *__restrict__ rgbx,
                                                               const uint2 *__restrict__ chunks, uint32_t cap,
-                                                              const uint32_t *__restrict__ counters, SplatCam cam,
+                                                              const uint32_t *__restrict__ counters, SplatCam cam_val,
+                                                              const SplatCam *__restrict__ cam_dev,
                                                               const uint64_t *__restrict__ key, float one_plus_eps,
                                                               uint32_t *__restrict__ acc) {
+  const SplatCam &cam = DEV ? *cam_dev : cam_val;
   uint2 ch;
   if (!work_item(blockIdx.x, counters, chunks, cap, &ch)) return;
   const float *P = cam.P;
@@ -932,15 +942,19 @@ TiledSplatGrid tiled_splat_grid(uint32_t W, uint32_t H, uint32_t n_points) {
 }
 
 hipError_t launch_tiled_splat(const CloudDev &c, const uint2 *chunks, uint32_t *counters, const SplatCam &cam,
-                              uint32_t H, const TiledSplatBufs &b, uint64_t *key, float *depth, uint32_t *rgba,
-                              int stage, hipStream_t s) {
+                              const SplatCam *cam_dev, uint32_t H, const TiledSplatBufs &b, uint64_t *key,
+                              float *depth, uint32_t *rgba, int stage, hipStream_t s) {
   if (c.max_chunks == 0) return hipErrorInvalidValue;  // a loaded cloud has at least one point
   const TiledSplatGrid g = tiled_splat_grid(cam.W, H, c.n);
   const TileGrid tg{g.tiles_x, g.tiles_y, g.n_tiles};
   switch (stage) {
     case 0:
-      bin_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, c.max_chunks, counters, cam, tg, b.recs,
-                                                  b.segs, b.tile_nseg);
+      if (cam_dev)
+        bin_kernel<true><<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, c.max_chunks, counters, cam, cam_dev,
+                                                          tg, b.recs, b.segs, b.tile_nseg);
+      else
+        bin_kernel<false><<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, chunks, c.max_chunks, counters, cam,
+                                                           nullptr, tg, b.recs, b.segs, b.tile_nseg);
       break;
     case 1:
       tilescan_kernel<<<1, kScanThreads, 0, s>>>(b.tile_nseg, tg, b.tile_off, b.tile_units, b.units,
@@ -964,10 +978,15 @@ hipError_t launch_tiled_splat(const CloudDev &c, const uint2 *chunks, uint32_t *
   return hipGetLastError();
 }
 
-hipError_t launch_cull(const CloudDev &c, const CullParams &prm, uint8_t *flags, uint2 *chunks, uint32_t *counters,
-                       hipStream_t s) {
+hipError_t launch_cull(const CloudDev &c, const CullParams &prm, const CullParams *prm_dev, uint8_t *flags,
+                       uint2 *chunks, uint32_t *counters, hipStream_t s) {
   const uint32_t nb = (c.n_cells + kThreads - 1) / kThreads;
-  cull_kernel<<<nb, kThreads, 0, s>>>(c.aabb, c.cell_start, c.n_cells, prm, flags, chunks, c.max_chunks, counters);
+  if (prm_dev)
+    cull_kernel<true><<<nb, kThreads, 0, s>>>(c.aabb, c.cell_start, c.n_cells, prm, prm_dev, flags, chunks,
+                                              c.max_chunks, counters);
+  else
+    cull_kernel<false><<<nb, kThreads, 0, s>>>(c.aabb, c.cell_start, c.n_cells, prm, nullptr, flags, chunks,
+                                               c.max_chunks, counters);
   return hipGetLastError();
 }
 
@@ -1013,12 +1032,18 @@ hipError_t launch_resolve(const uint64_t *key, const uint32_t *rgbx, float *dept
 }
 
 hipError_t launch_soft(const CloudDev &c, const uint2 *chunks, const uint32_t *counters, const SplatCam &cam,
-                       const uint64_t *key, float one_plus_eps, uint32_t *acc, float *depth, uint32_t *rgba,
-                       uint32_t npix, hipStream_t s) {
+                       const SplatCam *cam_dev, const uint64_t *key, float one_plus_eps, uint32_t *acc, float *depth,
+                       uint32_t *rgba, uint32_t npix, hipStream_t s) {
   clear_acc_kernel<<<grid_for(npix), kThreads, 0, s>>>(reinterpret_cast<uint4 *>(acc), npix);
   if (c.max_chunks)
-    soft_accum_kernel<<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, c.rgbx, chunks, c.max_chunks, counters, cam,
-                                                         key, one_plus_eps, acc);
+  {
+    if (cam_dev)
+      soft_accum_kernel<true><<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, c.rgbx, chunks, c.max_chunks, counters,
+                                                               cam, cam_dev, key, one_plus_eps, acc);
+    else
+      soft_accum_kernel<false><<<c.max_chunks, kThreads, 0, s>>>(c.x, c.y, c.z, c.rgbx, chunks, c.max_chunks,
+                                                                counters, cam, nullptr, key, one_plus_eps, acc);
+  }
   resolve_soft_kernel<<<grid_for(npix), kThreads, 0, s>>>(key, acc, depth, rgba, npix);
   return hipGetLastError();
 }

@@ -177,3 +177,22 @@ def test_two_context_frame_pipeline_equals_sequential(lnr, ctx, room_cloud, room
     torch.cuda.synchronize()
     for i, (a, b) in enumerate(zip(alone, outs)):
         assert torch.equal(a, b), f"frame {i} differs in the pipeline"
+
+
+def test_whole_batch_graph_replays_follow_new_cameras(lnr, ctx, room_scene, room_cloud):
+    """One lane, two sessions of one size: every step replays the one captured
+    graph of (96 x 128, batch 2) with the next cameras, written to device
+    memory before the replay.  Each of 6 replays, with the checks' own device
+    work in between, must equal the frames computed alone."""
+    blob = synth.make_unet_blob((16, 32, 64), seed=2)
+    net = lnr.lnr_unet_load(ctx, blob, lnr.LNR_FP32)
+    srv = lnr.lnr_server_create(ctx, room_cloud, net, max_batch=2, lanes=1, n_levels=3, filter_strength=0.5,
+                                use_graphs=True, max_width=128, max_height=96)
+    sids = [lnr.lnr_server_open_session(srv, 128, 96) for _ in range(2)]
+    cams = [synth.random_walk_path(room_scene, 6, seed=50 + i, width=128, height=96, fov_deg=80.0) for i in range(2)]
+    res = _serve_all(lnr, srv, sids, cams, 6)
+    assert all(b == 2 for _, b in res.values())
+    for f in range(6):
+        for i in range(2):
+            alone = _alone(lnr, ctx, room_cloud, net, cams[i][f], 3, 0.5)
+            assert np.array_equal(res[f * 100 + i][0], alone), f"session {i} frame {f}"
