@@ -829,6 +829,9 @@ def main():
     flops = {name: 2.0 * h * w * co * 9 * ci for (name, h, w, co, ci) in shapes}
     mfma_flops = {name: (2.0 * ((h + 1) // 2) * ((w + 1) // 2) * 16 * co * ci if i > 0 else 2.0 * h * w * co * 9 * 6)
                   for i, (name, h, w, co, ci) in enumerate(shapes)}
+    # the 16-bit modes run both first-level convolutions as one kernel (conv/enc0)
+    flops["conv/enc0"] = flops["conv/enc0a"] + flops["conv/enc0b"]
+    mfma_flops["conv/enc0"] = mfma_flops["conv/enc0a"] + mfma_flops["conv/enc0b"]
     head_flops = 2.0 * H * W * 3 * widths[0]
 
     def conv_roofline(kstats, prec, executed):
@@ -847,7 +850,7 @@ def main():
     dom, roofline = conv_roofline(ks, p0, exec_fp32)
     traffic = recorded_traffic(dom) if p0 == "fp32" else None
     roofline["traffic"] = None if traffic is None else round(traffic)
-    unet_flops = sum(flops.values()) + head_flops
+    unet_flops = sum(v for k, v in flops.items() if k != "conv/enc0") + head_flops
     n_proc = results[p0].get("processed_points_per_frame", proc0)
     gbytes = algorithmic_bytes(H, W, NL, n_proc, filled0, filled0 - kept0)
 
@@ -886,7 +889,7 @@ def main():
         ms = sum(v[0] for k, v in kp.items() if k.startswith("conv/") or k in ("pack", "head"))
         peak = PEAK_TFLOPS[peak_kind(p)]
         if p == "fp32":
-            ex = sum(mfma_flops.values()) + head_flops
+            ex = sum(v for k, v in mfma_flops.items() if k != "conv/enc0") + head_flops
         elif p in ("bf16x3", "fp8x3"):
             ex = 3.0 * unet_flops  # three passes per product
         else:

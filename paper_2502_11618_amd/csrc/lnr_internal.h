@@ -223,6 +223,11 @@ struct ConvCall {
 
 hipError_t launch_pack_input(const float *depth, const uint32_t *rgba, int H, int W, int cpad, Prec p, void *x,
                              hipStream_t s);
+// the first two convolutions in one launch (bf16 and fp16, first level of 16 or
+// 32 channels, at least two levels): the same outputs as two launch_conv3x3
+// calls, without the first one's output in HBM
+bool enc0_fusable(const ConvLayer &l0, const ConvLayer &l1, Prec p);
+hipError_t launch_enc0_fused(const ConvCall &c0, const ConvCall &c1, Prec p, hipStream_t s);
 hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s);
 hipError_t launch_head(const void *x, int C, int H, int W, const ConvLayer &head, Prec p, float *out, hipStream_t s);
 

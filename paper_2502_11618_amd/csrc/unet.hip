@@ -575,6 +575,265 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   }
 }
 
+// The network's first two convolutions in one kernel, for the 16-bit modes
+// (MODE 1 bf16, MODE 3 fp16) when the first level has at most 32 channels.
+// An output tile of 8 rows x 32 columns x 32 channels of the second
+// convolution needs the first convolution's output on a 10 x 34 pixel region
+// (its halo), which needs the network input on 12 x 36 pixels.  Phase 1 stages
+// that input and the first layer's weights in LDS and computes the first
+// convolution on the 340 region pixels (eleven 32-pixel MFMA blocks: ten region
+// rows of 32 columns and one block of the 20 pixels of the two right-hand
+// columns), with bias, ReLU and the same 16-bit rounding the unfused layer's
+// store applies, and zero where a region pixel lies outside the image (the
+// second layer's padding).  The result stays in LDS as the second layer's
+// staged input; phase 2 is the generic kernel's single-chunk K loop and
+// epilogue (ReLU output for the skip connection and its 2x2 max-pool) on it.
+// Both layers take their sums in the generic kernel's order, so the outputs
+// are bit-identical to the two unfused launches; the first layer's output
+// never goes to HBM.  CK1 = channels of the first level (16 or 32); RGBDA:
+// the input comes from the RGBDA image (a single image) instead of the
+// packed 16-channel input tensor.
+template <int MODE, int CK1, bool RGBDA>
+__global__ __launch_bounds__(256) void enc0_fused_kernel(ConvArgs a0, ConvArgs a1) {
+  static_assert(MODE == 1 || MODE == 3, "16-bit modes only");
+  using T = ConvTraits<MODE>;
+  using LT = typename T::L;
+  using InT = typename T::In;
+  constexpr int R = 2, TH = 4 * R, TW = 32;
+  constexpr int XW = TW + 4, XPix = (TH + 4) * XW;  // network input region
+  constexpr int MW = TW + 2, MPix = (TH + 2) * MW;  // first layer's output region
+  constexpr int C0 = 16, S0 = C0 + T::kPad, S1 = CK1 + T::kPad;
+  constexpr int WROWS = 9 * 32;
+  // LDS: [ input region | first-layer weights ] (phase 1), reused for the
+  // second layer's weights and then the output staging; [ region ] throughout
+  constexpr int A_ELEMS = XPix * S0 + WROWS * S0;
+  static_assert(WROWS * S1 <= A_ELEMS, "second-layer weights fit where phase 1 was");
+  __shared__ __attribute__((aligned(16))) LT s_a[A_ELEMS];
+  __shared__ __attribute__((aligned(16))) LT s_mid[MPix * S1];
+  LT *s_x = s_a, *s_w0 = s_a + XPix * S0, *s_w1 = s_a;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = lane & 31, h = lane >> 5;
+  const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
+  const int bimg = blockIdx.z;
+  const int H = a1.H, W = a1.W;
+  const InT *in0 = static_cast<const InT *>(a0.in0) + (size_t)bimg * a0.in0_bs;
+  InT *out = static_cast<InT *>(a1.out) + (size_t)bimg * a1.out_bs;
+  InT *out_pool = static_cast<InT *>(a1.out_pool) + (size_t)bimg * a1.pool_bs;
+
+  // ---- phase 1 staging: network input (16 channels per pixel), first-layer
+  // weights [32][9][16]; second-layer weights [32][9][CK1] go to registers now
+  // and to LDS after phase 1.  Every load is issued before the first use.
+  constexpr int NXP = (XPix + 255) / 256;               // input pixels per thread
+  constexpr int NV0 = WROWS * 2, NW0 = (NV0 + 255) / 256;  // first-layer weight vectors
+  constexpr int NV1 = WROWS * (CK1 / 8), NW1 = (NV1 + 255) / 256;
+  const uint16_t *w0 = static_cast<const uint16_t *>(a0.w);
+  const uint16_t *w1 = static_cast<const uint16_t *>(a1.w);
+  uint4 w0r[NW0], w1r[NW1];
+#pragma unroll
+  for (int k = 0; k < NW0; ++k) {
+    const int it = tid + 256 * k;
+    w0r[k] = it < NV0 ? *reinterpret_cast<const uint4 *>(w0 + (size_t)it * 8) : make_uint4(0u, 0u, 0u, 0u);
+  }
+#pragma unroll
+  for (int k = 0; k < NW1; ++k) {
+    const int it = tid + 256 * k;
+    w1r[k] = it < NV1 ? *reinterpret_cast<const uint4 *>(w1 + (size_t)it * 8) : make_uint4(0u, 0u, 0u, 0u);
+  }
+  bool xin[NXP];
+  size_t xo[NXP];
+#pragma unroll
+  for (int k = 0; k < NXP; ++k) {
+    const int pix = tid + 256 * k;
+    const int gy = ty0 - 2 + pix / XW, gx = tx0 - 2 + pix % XW;
+    xin[k] = pix < XPix && gy >= 0 && gy < H && gx >= 0 && gx < W;
+    xo[k] = xin[k] ? (size_t)gy * W + gx : 0;
+  }
+  if constexpr (RGBDA) {
+    uint32_t xc[NXP];
+    float xd[NXP];
+#pragma unroll
+    for (int k = 0; k < NXP; ++k) {
+      xc[k] = a0.rgbda_rgba[xo[k]];
+      xd[k] = a0.rgbda_depth[xo[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < NXP; ++k) {
+      const int pix = tid + 256 * k;
+      if (pix >= XPix) continue;
+      // network input x = (r/255, g/255, b/255, A ? D/16 : 0, A, 0, ...), as the input pack computes it
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (xin[k]) {
+        const uint32_t c = xc[k];
+        const bool A = (c >> 24) != 0;
+        const float x0 = (float)(c & 255u) / 255.0f, x1 = (float)((c >> 8) & 255u) / 255.0f;
+        const float x2 = (float)((c >> 16) & 255u) / 255.0f, x3 = A ? xd[k] * 0.0625f : 0.f, x4 = A ? 1.f : 0.f;
+        v = make_uint4(pack16x2<MODE>(x0, x1), pack16x2<MODE>(x2, x3), pack16x2<MODE>(x4, 0.f), 0u);
+      }
+      *reinterpret_cast<uint4 *>(&s_x[pix * S0]) = v;
+      *reinterpret_cast<uint4 *>(&s_x[pix * S0 + 8]) = make_uint4(0u, 0u, 0u, 0u);
+    }
+  } else {
+    uint4 xa[NXP], xb[NXP];
+#pragma unroll
+    for (int k = 0; k < NXP; ++k) {
+      const uint4 *src = reinterpret_cast<const uint4 *>(in0 + xo[k] * C0);
+      xa[k] = src[0];
+      xb[k] = src[1];
+    }
+#pragma unroll
+    for (int k = 0; k < NXP; ++k) {
+      const int pix = tid + 256 * k;
+      const uint32_t m = xin[k] ? ~0u : 0u;  // a pixel outside the image is zero
+      if (pix < XPix) {
+        *reinterpret_cast<uint4 *>(&s_x[pix * S0]) = make_uint4(xa[k].x & m, xa[k].y & m, xa[k].z & m, xa[k].w & m);
+        *reinterpret_cast<uint4 *>(&s_x[pix * S0 + 8]) = make_uint4(xb[k].x & m, xb[k].y & m, xb[k].z & m, xb[k].w & m);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NW0; ++k) {
+    const int it = tid + 256 * k;
+    if (it < NV0) *reinterpret_cast<uint4 *>(&s_w0[(it >> 1) * S0 + (it & 1) * 8]) = w0r[k];
+  }
+  __syncthreads();
+
+  // ---- phase 1: first convolution on the region, wave w takes blocks w, w + 4, w + 8
+  for (int blk = wv; blk < 11; blk += 4) {
+    // this lane's region pixel (mr, mc); lanes 20..31 of block 10 compute a
+    // copy of pixel (0, 32) and store nothing
+    const bool extra = blk == 10;
+    const bool live = !extra || n < 20;
+    const int mr = extra ? (live ? n >> 1 : 0) : blk;
+    const int mc = extra ? 32 + (n & 1) : n;
+    floatx16 acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+    const LT *bb = s_x + (mr * XW + mc) * S0 + 8 * h;
+    const LT *ab = s_w0 + n * 9 * S0 + 8 * h;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const uint4 av = *reinterpret_cast<const uint4 *>(ab + (dy * 3 + dx) * S0);
+        const uint4 bv = *reinterpret_cast<const uint4 *>(bb + (dy * XW + dx) * S0);
+        if constexpr (MODE == 1)
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv), acc, 0, 0, 0);
+        else
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(av), as_f16x8(bv), acc, 0, 0, 0);
+      }
+    // register 4j + i holds channel 8j + 4h + i of the lane's pixel
+    const int gy = ty0 - 1 + mr, gx = tx0 - 1 + mc;
+    const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+    if (live) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = 8 * j + 4 * h;
+        if (c >= CK1) continue;
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (inside && c < a0.cout) {
+          const float4 b = *reinterpret_cast<const float4 *>(a0.bias + c);
+          v[0] = fmaxf(acc[4 * j + 0] + b.x, 0.f);
+          v[1] = fmaxf(acc[4 * j + 1] + b.y, 0.f);
+          v[2] = fmaxf(acc[4 * j + 2] + b.z, 0.f);
+          v[3] = fmaxf(acc[4 * j + 3] + b.w, 0.f);
+        }
+        *reinterpret_cast<uint2 *>(&s_mid[(mr * MW + mc) * S1 + c]) =
+            make_uint2(pack16x2<MODE>(v[0], v[1]), pack16x2<MODE>(v[2], v[3]));
+      }
+    }
+  }
+  __syncthreads();  // phase 1's LDS reads are done: its space takes the second layer's weights
+#pragma unroll
+  for (int k = 0; k < NW1; ++k) {
+    const int it = tid + 256 * k;
+    if (it < NV1) {
+      const int row = it / (CK1 / 8), q = (it - row * (CK1 / 8)) * 8;
+      *reinterpret_cast<uint4 *>(&s_w1[row * S1 + q]) = w1r[k];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: second convolution, the generic kernel's K loop for one chunk
+  floatx16 acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[r][q] = 0.f;
+  {
+    constexpr int G = T::kGroup, HG = G / 2, NSTEP = (CK1 / G) * 3;
+    const LT *bbase = s_mid + (wv * R * MW + n) * S1 + HG * h;
+    const LT *abase = s_w1 + n * 9 * S1 + HG * h;
+#pragma unroll
+    for (int st = 0; st < NSTEP; ++st) {
+      const int g = st / 3, dx = st - 3 * g;
+      uint4 fa[3], fb[R + 2];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) fa[dy] = *reinterpret_cast<const uint4 *>(abase + g * G + (dy * 3 + dx) * S1);
+#pragma unroll
+      for (int i = 0; i < R + 2; ++i) fb[i] = *reinterpret_cast<const uint4 *>(bbase + g * G + (i * MW + dx) * S1);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if constexpr (MODE == 1)
+            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(fa[dy]), as_bf16x8(fb[r + dy]), acc[r], 0, 0, 0);
+          else
+            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(fa[dy]), as_f16x8(fb[r + dy]), acc[r], 0, 0, 0);
+        }
+    }
+  }
+
+  // ---- epilogue (as the generic kernel's, one 32-channel block): ReLU output
+  // staged per wave in LDS and written as 16-byte runs, and its 2x2 max-pool
+  constexpr int BM = 32, PSTR = BM * 2 + 16, STAGE = 4 * R * 32 * PSTR;
+  static_assert(STAGE <= (int)sizeof(s_a), "output staging fits");
+  __syncthreads();  // every wave is done with the second layer's weights
+  char *stage = reinterpret_cast<char *>(s_a) + wv * R * 32 * PSTR;
+  const int gx = tx0 + n, row0 = wv * R;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = 8 * j + 4 * h;
+    if (c >= a1.cout) continue;
+    const float4 b = *reinterpret_cast<const float4 *>(a1.bias + c);
+    const float bb[4] = {b.x, b.y, b.z, b.w};
+    float v[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[r][i] = fmaxf(acc[r][4 * j + i] + bb[i], 0.f);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      *reinterpret_cast<uint2 *>(stage + (r * 32 + n) * PSTR + c * 2) =
+          make_uint2(pack16x2<MODE>(v[r][0], v[r][1]), pack16x2<MODE>(v[r][2], v[r][3]));
+    // R = 2: rows 0 and 1 of the wave form one pooled row
+    float m[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      m[i] = fmaxf(v[0][i], v[1][i]);
+      m[i] = fmaxf(m[i], __shfl_xor(m[i], 1, 64));
+    }
+    const int gy = ty0 + row0;
+    if ((n & 1) == 0 && gy < H && gx < W)
+      *reinterpret_cast<uint2 *>(out_pool + ((size_t)(gy >> 1) * (W >> 1) + (gx >> 1)) * a1.cout + c) =
+          make_uint2(pack16x2<MODE>(m[0], m[1]), pack16x2<MODE>(m[2], m[3]));
+  }
+  {
+    // the wave reads back its own rows: 16-byte run s of pixel p of row r is
+    // item (r 32 + p) RUNS + s
+    constexpr int RUNS = BM / 8, ITEMS = R * 32 * RUNS;
+#pragma unroll
+    for (int it = 0; it < ITEMS / 64; ++it) {
+      const int item = it * 64 + lane, rp = item / RUNS, run = item - rp * RUNS;
+      const int r = rp >> 5, p = rp & 31;
+      const int gy = ty0 + row0 + r, gxx = tx0 + p, c = 8 * run;
+      const uint4 x = *reinterpret_cast<const uint4 *>(stage + rp * PSTR + run * 16);
+      if (gy < H && gxx < W && c < a1.cout)
+        *reinterpret_cast<uint4 *>(out + ((size_t)gy * W + gxx) * a1.cout + c) = x;
+    }
+  }
+}
+
 // 3x3 convolution in float32 by Winograd's minimal filtering F(2x2, 3x3): each
 // 2x2 block of output pixels is Y = A^T [sum_c U_c (.) V_c] A with
 // V_c = B^T d_c B the transform of the block's 4x4 input patch d_c of channel
@@ -1153,6 +1412,38 @@ hipError_t launch_conv3x3(const ConvCall &c, Prec p, hipStream_t s) {
     default: break;
   }
   return hipErrorInvalidValue;
+}
+
+bool enc0_fusable(const ConvLayer &l0, const ConvLayer &l1, Prec p) {
+  return (p == Prec::BF16 || p == Prec::FP16) && l0.cin_pad == 16 && l0.cout_pad == 32 && l1.cout_pad == 32 &&
+         l1.cin == l0.cout && l1.cin_pad == l1.cin && (l1.cin_pad == 16 || l1.cin_pad == 32);
+}
+
+hipError_t launch_enc0_fused(const ConvCall &c0, const ConvCall &c1, Prec p, hipStream_t s) {
+  const ConvLayer &L0 = *c0.layer, &L1 = *c1.layer;
+  if (!enc0_fusable(L0, L1, p) || !c1.out || !c1.out_pool || c1.head_out || c1.head_outs || c0.C1 || c1.C1 ||
+      c0.H != c1.H || c0.W != c1.W || c0.batch != c1.batch || (c0.rgbda_depth && (!c0.rgbda_rgba || c0.batch > 1)) ||
+      (!c0.rgbda_depth && c0.C0 != 16) || c1.C0 != L1.cin_pad)
+    return hipErrorInvalidValue;
+  const int batch = c0.batch < 1 ? 1 : c0.batch;
+  ConvArgs a0{c0.in0, nullptr, c0.C0, 0, c0.H, c0.W, L0.w, nullptr, L0.bias, L0.cout, L0.cin_pad, nullptr, nullptr,
+              nullptr, nullptr, nullptr, batch, c0.in0_bs, 0, 0, 0, nullptr, c0.rgbda_depth, c0.rgbda_rgba,
+              nullptr, nullptr};
+  ConvArgs a1{nullptr, nullptr, c1.C0, 0, c1.H, c1.W, L1.w, nullptr, L1.bias, L1.cout, L1.cin_pad, c1.out,
+              c1.out_pool, nullptr, nullptr, nullptr, batch, 0, 0, c1.out_bs, c1.pool_bs, nullptr, nullptr, nullptr,
+              nullptr, nullptr};
+  const dim3 grid((c1.W + 31) / 32, (c1.H + 7) / 8, batch);
+  const bool rgbda = c0.rgbda_depth != nullptr;
+#define LNR_ENC0(M, CK, RG) enc0_fused_kernel<M, CK, RG><<<grid, 256, 0, s>>>(a0, a1)
+  if (p == Prec::FP16) {
+    if (L1.cin_pad == 32) { if (rgbda) LNR_ENC0(3, 32, true); else LNR_ENC0(3, 32, false); }
+    else { if (rgbda) LNR_ENC0(3, 16, true); else LNR_ENC0(3, 16, false); }
+  } else {
+    if (L1.cin_pad == 32) { if (rgbda) LNR_ENC0(1, 32, true); else LNR_ENC0(1, 32, false); }
+    else { if (rgbda) LNR_ENC0(1, 16, true); else LNR_ENC0(1, 16, false); }
+  }
+#undef LNR_ENC0
+  return hipGetLastError();
 }
 
 hipError_t launch_head(const void *x, int C, int H, int W, const ConvLayer &head, Prec p, float *out, hipStream_t s) {
