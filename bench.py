@@ -18,6 +18,7 @@ oracle on sampled windows.  Prints one JSON line on stdout.
 from __future__ import annotations
 
 import argparse
+import contextlib
 import json
 import os
 import platform
@@ -96,13 +97,60 @@ def host_info():
     return info
 
 
-def cpu_baseline(scene, cam, blob, n_levels, fs, widths):
+_GEO = {}
+
+
+def _geo_frame(i):
+    """One frame's oracle projection + resolve + depth filter in a forked worker
+    (one thread); the grid and cameras come from the parent through fork."""
+    from oracle import depth_filter as F
+    from oracle import render as R
+    g, cams, n_levels, fs = _GEO["g"], _GEO["cams"], _GEO["n_levels"], _GEO["fs"]
+    cam = cams[i % len(cams)]
+    _, depth, rgba = R.render(g, cam)
+    F.depth_filter(depth.reshape(cam.height, cam.width), rgba.reshape(cam.height, cam.width, 4), n_levels, fs)
+    return i
+
+
+def cpu_geometry_all_cores(scene, cams, n_levels, fs):
+    """The oracle's projection + resolve + depth filter, one frame per host
+    core at once (forked worker processes, numpy single-threaded, at most 15
+    of them).  Called before the process touches the GPU, so the workers fork
+    from a process without a device context.  Returns the oracle grid (reused
+    by cpu_baseline) and the leg."""
+    import multiprocessing as mp
+    from oracle import grid as G
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    g = G.partition(scene.xyz, scene.rgb, 1.0)
+    try:
+        ncores = max(1, min(len(os.sched_getaffinity(0)), 15, len(cams)))
+        _GEO.update(g=g, cams=cams, n_levels=n_levels, fs=fs)
+        one_thread = threadpool_limits(limits=1) if threadpool_limits is not None else contextlib.nullcontext()
+        with one_thread, mp.get_context("fork").Pool(ncores) as pool:
+            t0 = time.perf_counter()
+            pool.map(_geo_frame, range(ncores), chunksize=1)
+            t = time.perf_counter() - t0
+        leg = {"frames": ncores, "processes": ncores, "wall_s": round(t, 3), "frames_per_s": round(ncores / t, 3)}
+    except Exception as e:  # pragma: no cover - a host without fork
+        leg = {"error": str(e)}
+    finally:
+        _GEO.clear()
+    return g, leg
+
+
+def cpu_baseline(scene, cams, blob, n_levels, fs, widths, pre=None):
     """The CPU oracle as it stands, on a bounded sample of the workload: the
     projection + resolve + depth filter of frame 0 over all points (numpy, one
-    thread), and the float64 U-Net on a centre crop, once with one BLAS thread
-    and once with every core, scaled by pixel count to the full frame (a full
-    1080p frame takes several minutes in float64, so the U-Net leg is
-    extrapolated and flagged as such)."""
+    thread), the same for one frame per core in forked single-threaded workers
+    (the all-core rate of the geometric part, measured beforehand by
+    cpu_geometry_all_cores: pre = its result), and the float64 U-Net on a
+    centre crop, once with one BLAS thread and once with every core, scaled by
+    pixel count to the full frame (a full 1080p frame takes several minutes in
+    float64, so the U-Net leg is extrapolated and flagged as such)."""
+    cam = cams[0]
     import numpy as np
     from oracle import depth_filter as F
     from oracle import grid as G
@@ -113,7 +161,7 @@ def cpu_baseline(scene, cam, blob, n_levels, fs, widths):
         all_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         threadpool_limits, all_threads = None, 1
-    g = G.partition(scene.xyz, scene.rgb, 1.0)
+    g, geo_all = pre if pre is not None else (G.partition(scene.xyz, scene.rgb, 1.0), None)
     t0 = time.perf_counter()
     _, depth, rgba = R.render(g, cam)
     H, W = cam.height, cam.width
@@ -144,7 +192,7 @@ def cpu_baseline(scene, cam, blob, n_levels, fs, widths):
                    f"({t_all:.2f} s with {all_threads} BLAS threads) scaled by pixel count to {W}x{H} "
                    f"({s_all:.1f} s extrapolated)"),
         "seconds_per_frame": round(t_geo + s_all, 3),
-        "legs": {"geometry_s": round(t_geo, 3), "geometry_threads": 1,
+        "legs": {"geometry_s": round(t_geo, 3), "geometry_threads": 1, "geometry_all_cores": geo_all,
                  "unet_all_cores_s": round(s_all, 1), "unet_all_cores_threads": int(all_threads),
                  "unet_all_cores_crop": c_all,
                  "unet_one_thread_s": round(s_one, 1), "unet_one_thread_crop": c_one,
@@ -669,6 +717,10 @@ def main():
     log(f"scene {scene.name}: {scene.n} points ({time.perf_counter() - t0:.1f} s)")
     cams = synth.orbit_path(scene, 120, W, H, FOV)
     blob = synth.make_unet_blob(widths, seed=0)
+    geo_pre = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle's projection and filter on every core ...")
+        geo_pre = cpu_geometry_all_cores(scene, cams, NL, FS)
 
     torch.cuda.set_device(0)
     ctx = L.lnr_context_create(0)
@@ -953,7 +1005,7 @@ def main():
                                                        "mean_batch", "megapixels_per_s")} for r in sweep]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        line["cpu_baseline"] = cpu_baseline(scene, cams[0], blob, NL, FS, widths)
+        line["cpu_baseline"] = cpu_baseline(scene, cams, blob, NL, FS, widths, geo_pre)
     print(json.dumps(line), flush=True)
 
 
