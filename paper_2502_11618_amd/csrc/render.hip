@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kThreads) void clear_kernel(uint64_t *__restrict__ 
 // visible unless some half-space's maximum over it is below -slack (all in
 // double, in the order below).  If visible, *bucket is the depth bucket of the
 // box centre.
-__device__ inline bool cell_visible(const CullParams &prm, double lo0, double lo1, double lo2, double hi0,
+__device__ __attribute__((always_inline)) inline bool cell_visible(const CullParams &prm, double lo0, double lo1, double lo2, double hi0,
                                     double hi1, double hi2, int *bucket) {
   bool vis = true;
   if (!prm.no_cull) {
@@ -68,22 +68,37 @@ __device__ inline bool cell_visible(const CullParams &prm, double lo0, double lo
 
 // Queue places for this lane's nch work items in queue `bucket`: the first
 // one's place within that queue.  Compaction without LDS atomics: per depth
-// bucket present in the wave, a wave-wide exclusive prefix (shuffle scan) of
-// the lanes' work-item counts places each cell within the wave's run; the
+// bucket present in the wave, a wave-wide exclusive prefix of the lanes'
+// work-item counts (a ballot and a count of the set lanes below when every
+// cell has at most one work item, else a shuffle scan) places each cell
+// within the wave's run; the
 // runs of the block's waves follow each other in wave order through LDS, and
 // one global atomic per bucket and block reserves the block's run.  Every
 // thread of the block calls it (block barriers).
-__device__ inline uint32_t reserve_places(uint32_t nch, int bucket, uint32_t *__restrict__ counters) {
+__device__ __attribute__((always_inline)) inline uint32_t reserve_places(uint32_t nch, int bucket, uint32_t *__restrict__ counters) {
   constexpr int kWaves = kThreads / 64;
   __shared__ uint32_t s_wave[kWaves][kDepthBuckets], s_base[kDepthBuckets];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t present = nch ? (1u << bucket) : 0u;  // buckets of this wave's visible cells
   for (int off = 32; off > 0; off >>= 1) present |= __shfl_xor(present, off, 64);
+  // lanes whose cell has more than one work item: with none in the wave (the
+  // common case), a bucket's prefix is a ballot and a count of the lanes below
+  const bool multi = __ballot(nch > 1) != 0;
+  const uint64_t below = (1ull << lane) - 1ull;
   uint32_t local = 0;
-  for (int b = 0; b < kDepthBuckets; ++b) {
-    uint32_t tot = 0;
-    if (present & (1u << b)) {  // the same for the whole wave
-      const uint32_t v = bucket == b ? nch : 0u;
+  if (lane < kDepthBuckets) s_wave[wave][lane] = 0u;  // buckets absent from the wave
+  // one pass per bucket present in the wave (the set is the same for every
+  // lane; the loop stays rolled, which keeps this short-lived kernel small)
+#pragma unroll 1
+  for (uint32_t m = __builtin_amdgcn_readfirstlane(present); m; m &= m - 1) {
+    const int b = __builtin_ctz(m);
+    const uint32_t v = bucket == b ? nch : 0u;
+    uint32_t tot;
+    if (!multi) {
+      const uint64_t bal = __ballot(v != 0);
+      if (v) local = (uint32_t)__popcll(bal & below);
+      tot = (uint32_t)__popcll(bal);
+    } else {
       uint32_t incl = v;
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
@@ -113,7 +128,7 @@ __device__ inline uint32_t reserve_places(uint32_t nch, int bucket, uint32_t *__
 
 // Frame totals: work items, visible cells and their points, reduced per wave
 // with one atomic per wave.
-__device__ inline void add_totals(bool vis, uint32_t nch, uint32_t cnt, uint32_t *__restrict__ counters) {
+__device__ __attribute__((always_inline)) inline void add_totals(bool vis, uint32_t nch, uint32_t cnt, uint32_t *__restrict__ counters) {
   uint32_t wave_chunks = nch;
   for (int off = 32; off > 0; off >>= 1) wave_chunks += __shfl_xor(wave_chunks, off, 64);
   const uint64_t vis_mask = __ballot(vis);
@@ -251,7 +266,7 @@ __device__ inline uint32_t small_div(uint32_t p, float inv_w) {
 
 // Point j at (x, y, z) through the camera: true if drawn, with its key
 // (depth bits << 32 | j) and pixel.
-__device__ inline bool project_point(float x, float y, float z, uint32_t j, const SplatCam &cam, uint64_t &k,
+__device__ __attribute__((always_inline)) inline bool project_point(float x, float y, float z, uint32_t j, const SplatCam &cam, uint64_t &k,
                                      uint32_t &px, uint32_t &py) {
   const float *P = cam.P;
   const float a = ((P[0] * x + P[1] * y) + P[2] * z) + P[3];
@@ -272,7 +287,7 @@ __device__ inline bool project_point(float x, float y, float z, uint32_t j, cons
 
 // The block-wide rectangle of the lanes' rectangles [x0, x1] x [y0, y1]
 // (x0 > x1 if none).  Contains block barriers.
-__device__ inline void block_rect(uint32_t x0, uint32_t y0, uint32_t x1, uint32_t y1, uint32_t *s_bb, uint32_t *rx0,
+__device__ __attribute__((always_inline)) inline void block_rect(uint32_t x0, uint32_t y0, uint32_t x1, uint32_t y1, uint32_t *s_bb, uint32_t *rx0,
                                   uint32_t *ry0, uint32_t *rx1, uint32_t *ry1) {
   for (int off = 32; off > 0; off >>= 1) {
     x0 = min(x0, (uint32_t)__shfl_xor(x0, off, 64));
@@ -339,7 +354,7 @@ __device__ inline void project_work_item(const float *__restrict__ xs, const flo
 // zb over the rectangle when it has at most kDedupPx pixels, else point by
 // point.  Contains block barriers.
 template <bool COUNT>
-__device__ inline void splat_block(const uint64_t (&kk)[kPtsPerThread], const uint32_t (&px)[kPtsPerThread],
+__device__ __attribute__((always_inline)) inline void splat_block(const uint64_t (&kk)[kPtsPerThread], const uint32_t (&px)[kPtsPerThread],
                                    const uint32_t (&py)[kPtsPerThread], uint32_t x0, uint32_t y0, uint32_t x1,
                                    uint32_t y1, uint32_t W, uint64_t *__restrict__ key, unsigned long long *zb,
                                    uint32_t &issued) {
