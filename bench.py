@@ -314,7 +314,8 @@ def recorded_traffic(kernel):
 def serve_bench(L, scene, cloud, blob, seconds, n_sessions=64, seed=0, budget=32 << 30, max_batch=8, lanes=2):
     """Serving: n_sessions viewers with seeded random-walk cameras at resolutions
     drawn from {640x480, 1280x720, 1920x1080}, Poisson arrivals at U(30, 90) Hz
-    per session, bf16 U-Net, admitted under an HBM budget; continuous batching
+    per session, fp16 U-Net (the 16-bit mode within the 2e-2 bound; plain bf16
+    runs at the same speed but misses it), admitted under an HBM budget; continuous batching
     of same-resolution requests across sessions.  Latency = host time from
     submit to the poll that sees the frame finished; a request replaced by a
     newer camera of its session before it ran is superseded, and its wait
@@ -324,7 +325,7 @@ def serve_bench(L, scene, cloud, blob, seconds, n_sessions=64, seed=0, budget=32
     rng = np.random.default_rng(seed)
     sizes = [(640, 480), (1280, 720), (1920, 1080)]
     sctx = L.lnr_context_create(0, budget)
-    net = L.lnr_unet_load(sctx, blob, L.LNR_BF16)
+    net = L.lnr_unet_load(sctx, blob, L.LNR_FP16)
     srv = L.lnr_server_create(sctx, cloud, net, max_batch=max_batch, lanes=lanes, n_levels=5, filter_strength=0.5,
                               use_graphs=True, max_width=1920, max_height=1080)
     sess = []
@@ -401,7 +402,7 @@ def serve_bench(L, scene, cloud, blob, seconds, n_sessions=64, seed=0, budget=32
         "superseded_wait_ms": {"p50": pct(sup_ms, 50), "p99": pct(sup_ms, 99)},
         "mean_batch": round(float(np.mean(batches)), 2) if batches else None,
         "frames_by_resolution": per_res, "budget_bytes": budget, "max_batch": max_batch, "lanes": lanes,
-        "precision": "bf16",
+        "precision": "fp16",
     }
 
 
