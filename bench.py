@@ -200,6 +200,48 @@ def cpu_baseline(scene, cams, blob, n_levels, fs, widths, pre=None):
     }
 
 
+def parity_every_10th(L, ctx, cloud, net_fp32, cams, g, blob, H, W, n_levels, fs, progress=None):
+    """Parity along the path, outside the timed region: every 10th frame's key,
+    depth and rgba after the projection and the depth filter bit for bit
+    against the oracle, and the fp32 U-Net on one seeded 64x64 window of each
+    against the float64 oracle (computed on a crop grown by the receptive
+    margin)."""
+    import numpy as np
+    import torch
+    from oracle import depth_filter as F
+    from oracle import render as R
+    from oracle import unet as U
+    net = U.parse_blob(blob)
+    rng = np.random.default_rng(10)
+    img = L.Image(H, W)
+    out = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
+    frames, bad, max_abs = [], [], 0.0
+    for i in range(0, len(cams), 10):
+        cam = cams[i]
+        L.lnr_render(ctx, cloud, cam, img)
+        key = img.key.cpu().numpy().view(np.uint64).copy()
+        L.lnr_depth_filter(ctx, img, n_levels, fs)
+        L.lnr_reconstruct(ctx, net_fp32, img, out)
+        torch.cuda.synchronize()
+        d, r = img.depth.cpu().numpy(), img.rgba.cpu().numpy()
+        k_ref, depth, rgba = R.render(g, cam)
+        fd, fr, _ = F.depth_filter(depth.reshape(H, W), rgba.reshape(H, W, 4), n_levels, fs)
+        if not (np.array_equal(key, k_ref.reshape(-1)) and np.array_equal(d.view(np.uint32), fd.view(np.uint32))
+                and np.array_equal(r, fr)):
+            bad.append(i)
+        y0, x0 = int(rng.integers(0, H - 64)), int(rng.integers(0, W - 64))
+        ref = U.forward_crop(net, fd, fr, y0, y0 + 64, x0, x0 + 64)
+        e = float(np.abs(out[:, y0:y0 + 64, x0:x0 + 64].cpu().numpy().astype(np.float64) - ref).max())
+        max_abs = max(max_abs, e)
+        frames.append(i)
+        if progress is not None:
+            progress(f"parity frame {i}: projection and filter {'bit-exact' if i not in bad else 'DIFFER'}, "
+                     f"fp32 U-Net window max-abs {e:.2e}")
+    return {"frames": frames, "projection_and_filter_bit_exact": not bad, "frames_differing": bad,
+            "unet_fp32_window_max_abs": max_abs, "unet_fp32_bound": TOL["fp32"],
+            "unet_fp32_within_bound": max_abs <= TOL["fp32"]}
+
+
 def sampled_error(fd, fr, blob, outs, H, W, progress=None, tol=None):
     """max-abs and PSNR of each precision's output against the float64 oracle on
     three 64x64 windows (centre, a corner, an edge), each computed on a crop
@@ -976,6 +1018,7 @@ def main():
                    "grid_dims": list(info["dims"]), "pipelined": bool(args.pipelined)},
         "latency_ms": {k: round(v, 4) for k, v in results[p0]["latency_ms"].items()},
         "points_per_s": round(n_proc * fps, 1),
+        "points_per_s_projection": round(n_proc / (sum(ks[k][0] for k in RENDER_KERNELS if k in ks) * 1e-3), 1),
         "processed_points_per_frame": round(n_proc, 1),
         "precisions": {p: {"frames_per_s": round(r["frames_per_s"], 3), "ms_per_frame": round(r["ms_per_frame"], 4),
                            "latency_ms": {k: round(v, 4) for k, v in r["latency_ms"].items()},
@@ -992,6 +1035,14 @@ def main():
         "per_frame": per_frame,
         "env": host_info(),
     }
+    if not args.no_error_check and "fp32" in nets:
+        log("parity of every 10th frame of the path against the oracle ...")
+        g_or = geo_pre[0] if geo_pre is not None else None
+        if g_or is None:
+            from oracle import grid as G
+            g_or = G.partition(scene.xyz, scene.rgb, 1.0)
+        line["parity_every_10th_frame"] = parity_every_10th(L, ctx, cloud, nets["fp32"], cams, g_or, blob, H, W,
+                                                            NL, FS, progress=log)
     try:
         line["env"]["gpu"] = torch.cuda.get_device_name(0)
         line["env"]["cus"] = torch.cuda.get_device_properties(0).multi_processor_count
