@@ -509,7 +509,7 @@ def largest_scene(args):
     """The largest configuration: 300M points from 16 scans of an 80 x 60 x 10 m
     scene of 32 rooms (2 m cells); batches of 8 consecutive orbit-path views at
     3840x2160; depth filter n = 6, fs = 0.5; U-Net widths 32/64/128/256/512 in
-    fp32, fp16, split bf16, bf16, split e4m3 and e4m3, each judged by its own
+    fp32, fp16, split bf16, bf16, split e4m3 and e4m3, each held to its own
     bound (e4m3: 8e-2).  A batch renders, filters and reconstructs its
     8 views one after the other into 8 output images (a 4K view fills the GPU
     on its own).  Reports views/s, batch time, per-view latency, the U-Net's
