@@ -188,8 +188,9 @@ lnr_status lnr_render_soft(lnr_context *ctx, const lnr_cloud *c, const lnr_camer
  * every camera of the batch).  outs[v] receives exactly what lnr_render of
  * cams[v] alone writes, bit for bit, for every v.
  *   cams, outs : HOST arrays of n_views cameras and images (the images'
- *                buffers are device buffers, as for lnr_render); the views'
- *                key buffers must not overlap (LNR_E_INVALID_ARG).
+ *                buffers are device buffers, as for lnr_render); no two
+ *                of the views' buffers (key, depth and rgba of every view)
+ *                may overlap (LNR_E_INVALID_ARG).
  *   n_views    : 1..1024.  The views go in passes of up to 8: a pass culls
  *                every grid cell against each of its views' frustums, and
  *                the points of a cell visible in any of them are loaded once

@@ -830,15 +830,22 @@ lnr_status lnr_render_views(lnr_context *ctx, const lnr_cloud *c, const lnr_came
   lnr_status st;
   for (int v = 0; v < n_views; ++v)
     if ((st = check_target(ctx, &cams[v], &outs[v])) != LNR_OK) return st;
-  // views that shared key buffers would mix their z-buffers
-  for (int v = 0; v < n_views; ++v) {
-    const uintptr_t a0 = reinterpret_cast<uintptr_t>(outs[v].key);
-    const uintptr_t a1 = a0 + 8ull * (uint64_t)outs[v].width * (uint64_t)outs[v].height;
-    for (int u = 0; u < v; ++u) {
-      const uintptr_t b0 = reinterpret_cast<uintptr_t>(outs[u].key);
-      const uintptr_t b1 = b0 + 8ull * (uint64_t)outs[u].width * (uint64_t)outs[u].height;
-      if (a0 < b1 && b0 < a1) return fail(ctx, LNR_E_INVALID_ARG, "two views' key buffers overlap");
+  // the views are drawn together: no two of their buffers (key, depth, rgba
+  // of every view) may overlap
+  {
+    std::vector<std::pair<uintptr_t, uintptr_t>> r;
+    r.reserve(3 * (size_t)n_views);
+    for (int v = 0; v < n_views; ++v) {
+      const uint64_t np = (uint64_t)outs[v].width * (uint64_t)outs[v].height;
+      const uintptr_t k = reinterpret_cast<uintptr_t>(outs[v].key), d = reinterpret_cast<uintptr_t>(outs[v].depth),
+                      c = reinterpret_cast<uintptr_t>(outs[v].rgba);
+      r.emplace_back(k, k + 8 * np);
+      r.emplace_back(d, d + 4 * np);
+      r.emplace_back(c, c + 4 * np);
     }
+    std::sort(r.begin(), r.end());
+    for (size_t i = 1; i < r.size(); ++i)
+      if (r[i].first < r[i - 1].second) return fail(ctx, LNR_E_INVALID_ARG, "the views' image buffers overlap");
   }
   if (c->ctx->device != ctx->device) return fail(ctx, LNR_E_INVALID_ARG, "cloud lives on another device");
   if ((st = use_device(ctx)) != LNR_OK) return st;

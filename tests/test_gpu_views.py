@@ -130,8 +130,12 @@ def test_views_reject_bad_arguments_before_drawing(lnr, ctx, room_cloud, room_ca
 
     imgs = [sentinel(c) for c in cams]
     bad_size = [imgs[0], imgs[1], lnr.Image(cams[2].height + 1, cams[2].width)]
+    # a third view whose depth plane is the second view's
+    shared_depth = lnr.Image.from_tensors(imgs[1].depth, lnr.Image(cams[2].height, cams[2].width).rgba,
+                                          lnr.Image(cams[2].height, cams[2].width).key)
     for args, what in [((cams, bad_size, 0), "size of the last view"),
                        ((cams, [imgs[0], imgs[1], imgs[0]], 0), "shared key buffer"),
+                       ((cams, [imgs[0], imgs[1], shared_depth], 0), "shared depth buffer"),
                        ((cams, imgs, lnr.LNR_RENDER_ATOMIC_SPLAT), "flag"),
                        ((cams[:0], imgs[:0], 0), "no view")]:
         with pytest.raises(lnr.LnrError) as e:
