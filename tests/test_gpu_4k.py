@@ -64,13 +64,15 @@ def test_4k_five_level_unet_sampled_windows(lnr, ctx, four_k, prec):
     check_unet_error(prec, worst, "4k windows")
 
 
-def test_4k_batch_of_eight_views_equals_alone(lnr, ctx, four_k):
-    """Eight 4K views in one batch (bf16 U-Net, widths[0] = 32 so the head is
-    fused and every view writes its own output)."""
+@pytest.mark.parametrize("prec,graphs", [("LNR_BF16", False), ("LNR_FP16", True)])
+def test_4k_batch_of_eight_views_equals_alone(lnr, ctx, four_k, prec, graphs):
+    """Eight 4K views in one batch (widths[0] = 32, so the head is fused and
+    every view writes its own output), launched directly or as one captured
+    graph of the whole batch."""
     import torch
-    net = lnr.lnr_unet_load(ctx, four_k["blob"], lnr.LNR_BF16)
+    net = lnr.lnr_unet_load(ctx, four_k["blob"], getattr(lnr, prec))
     srv = lnr.lnr_server_create(ctx, four_k["cloud"], net, max_batch=8, lanes=1, n_levels=NL, filter_strength=FS,
-                                use_graphs=False, max_width=W, max_height=H)
+                                use_graphs=graphs, max_width=W, max_height=H)
     sids = [lnr.lnr_server_open_session(srv, W, H) for _ in range(8)]
     cams = [synth.random_walk_path(four_k["scene"], 1, seed=200 + i, width=W, height=H, fov_deg=FOV)[0]
             for i in range(8)]
@@ -116,4 +118,24 @@ def test_4k_largest_scene_layout_bit_exact(lnr, ctx, frame):
     torch.cuda.synchronize()
     _, gd, gr = image_to_host(img)
     assert_images_equal((None, gd, gr), (None, fd, fr), f"largest-layout filter {frame}")
+    lnr.lnr_cloud_destroy(cloud)
+
+
+def test_4k_eight_views_in_one_pass(lnr, ctx):
+    """The largest configuration's building at 4M points: 8 consecutive 4K
+    orbit views projected in one pass (lnr_render_views) equal each view
+    rendered alone, and views 0 and 7 equal the oracle, bit for bit."""
+    import torch
+    scene = synth.scene_for_config("huge", seed=0, n_points=4_000_000)
+    cloud = lnr.lnr_cloud_load(ctx, scene.xyz, scene.rgb, 2.0)
+    cams = synth.orbit_path(scene, 120, W, H, FOV)[40:48]
+    imgs = [lnr.Image(H, W) for _ in cams]
+    lnr.lnr_render_views(ctx, cloud, cams, imgs)
+    torch.cuda.synchronize()
+    g = G.partition(scene.xyz, scene.rgb, 2.0)
+    for v, cam in enumerate(cams):
+        got = image_to_host(imgs[v])
+        assert_images_equal(got, image_to_host(render_gpu(lnr, ctx, cloud, cam)), f"view {v} vs alone")
+        if v in (0, 7):
+            assert_images_equal(got, R.render(g, cam), f"view {v} vs oracle")
     lnr.lnr_cloud_destroy(cloud)
