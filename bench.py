@@ -625,13 +625,16 @@ def largest_scene(args):
                       "multi_view_render": mv, "results": res, "env": host_info()}), flush=True)
 
 
-def precision_tier(args):
+def precision_tier(args, scene_name="large", n_points=None, sizes=((1920, 1080), (2560, 1440)),
+                   workload="large-100M-pts-8-scans-orbit", mode="precision-tier"):
     """The precision tier on the larger scene: 100M points from 8 scans (1 m
     cells), 60 frames of the orbit path at 1920x1080 and at 2560x1440, depth
     filter n = 5, fs = 0.5, U-Net 32/64/128/256 in fp32, fp16, split bf16,
     bf16, split e4m3 and e4m3:
     frames/s, per-frame latency and the sampled error against the float64
-    oracle of each precision.  Prints one JSON line."""
+    oracle of each precision.  With other arguments, the same run on another
+    scene and other image sizes (the paper's Table 1 shapes: the multi-room
+    generator at 23M points, 1920x1440 and 960x720).  Prints one JSON line."""
     import numpy as np
     import torch
     import paper_2502_11618_amd as L
@@ -640,7 +643,7 @@ def precision_tier(args):
     FOV, NL, FS, STEPS = 90.0, 5, 0.5, 60
     widths = (32, 64, 128, 256)
     t0 = time.perf_counter()
-    scene = synth.scene_for_config("large", seed=0)
+    scene = synth.scene_for_config(scene_name, seed=0, n_points=n_points)
     log(f"scene {scene.name}: {scene.n} points ({time.perf_counter() - t0:.1f} s)")
     blob = synth.make_unet_blob(widths, seed=0)
     ctx = L.lnr_context_create(0)
@@ -651,7 +654,7 @@ def precision_tier(args):
                 "fp8x3": L.LNR_FP8_E4M3X3, "fp8": L.LNR_FP8_E4M3}
     nets = {p: L.lnr_unet_load(ctx, blob, i) for p, i in prec_ids.items()}
     out_all = {}
-    for W, H in ((1920, 1080), (2560, 1440)):
+    for W, H in sizes:
         cams = synth.orbit_path(scene, 120, W, H, FOV)
         img = L.Image(H, W)
         out = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
@@ -691,7 +694,7 @@ def precision_tier(args):
             res[p]["error_vs_fp64_sampled"] = err[p]
         out_all[f"{W}x{H}"] = {"processed_points_frame0": proc, "precisions": res}
         log(f"{W}x{H}: " + ", ".join(f"{p} {r['frames_per_s']} f/s" for p, r in res.items()))
-    print(json.dumps({"mode": "precision-tier", "workload": "large-100M-pts-8-scans-orbit",
+    print(json.dumps({"mode": mode, "workload": workload,
                       "points": scene.n, "cell_m": 1.0, "load_partition_s": round(load_s, 3), "n_levels": NL,
                       "filter_strength": FS, "unet_widths": list(widths), "steps": STEPS, "results": out_all,
                       "env": host_info()}), flush=True)
@@ -711,10 +714,12 @@ def main():
                          "current frame's U-Net (default: frames one after the other on one stream)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="serving run length per session count of the sweep (0 = skip)")
-    ap.add_argument("--mode", default="frames", choices=["frames", "copy", "counters", "precision-tier", "largest"],
+    ap.add_argument("--mode", default="frames",
+                    choices=["frames", "copy", "counters", "precision-tier", "paper-shapes", "largest"],
                     help="copy: only a plain 1 GiB device copy (calibrates HBM byte counters); "
                          "counters: summarise rocprofv3 FETCH_SIZE/WRITE_SIZE csv files (no GPU); "
                          "precision-tier: the 100M-point scene at 1080p and 1440p in every precision; "
+                         "paper-shapes: the multi-room scene at 23M points, 1920x1440 and 960x720, every precision; "
                          "largest: the 300M-point scene, batches of 8 views at 3840x2160, 5-level U-Net")
     ap.add_argument("--projection-only", action="store_true",
                     help="largest mode: stop after comparing view-by-view and multi-view projection")
@@ -736,6 +741,10 @@ def main():
 
     if args.mode == "precision-tier":
         precision_tier(args)
+        return
+    if args.mode == "paper-shapes":
+        precision_tier(args, "multiroom", 23_000_000, ((1920, 1440), (960, 720)),
+                       "multiroom-23M-pts-1920x1440-and-960x720-orbit", "paper-shapes")
         return
     if args.mode == "largest":
         largest_scene(args)
