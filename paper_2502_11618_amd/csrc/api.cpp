@@ -781,7 +781,10 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   if (soft && (st = ensure(ctx, scr.soft_acc, 16ull * npix)) != LNR_OK) return st;
   const TiledSplatBufs tb = tiled_bufs(scr);
   if (dev && atomic) return fail(ctx, LNR_E_INVALID_ARG, "a camera in device memory needs the tiled splat");
-  LNR_LAUNCH(ctx, "clear", s, launch_clear(out->key, npix, counters, tb.tile_nseg, atomic ? 0u : tg.n_tiles, s));
+  // (the tiled splat writes every key itself: its segment sort empties the
+  // keys of the tiles that merge through atomics, so only the counters here)
+  LNR_LAUNCH(ctx, "clear", s,
+             launch_clear(out->key, atomic ? npix : 0u, counters, tb.tile_nseg, atomic ? 0u : tg.n_tiles, s));
   LNR_LAUNCH(ctx, "cull", s,
              launch_cull(c->d, prm, dev ? &dev->cull : nullptr, static_cast<uint8_t *>(scr.flags.p),
                          static_cast<uint2 *>(scr.chunks.p), counters, s));

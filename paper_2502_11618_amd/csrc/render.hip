@@ -471,7 +471,8 @@ __global__ __launch_bounds__(kThreads) void splat_views_kernel(const float *__re
 //             array.  Each (work item, tile) group is a segment.
 //   tilescan  one workgroup: per-tile segment offsets, and the units of work
 //             of the tile kernel: up to kSegsPerUnit segments of one tile.
-//   segsort   groups the segment ids by tile.
+//   segsort   groups the segment ids by tile, and empties the keys of the
+//             tiles of more than one unit (the only keys not written whole).
 //   tile      one workgroup per unit: LDS z-buffer of the tile over the
 //             unit's records.  A tile of one unit owns its pixels and writes
 //             key, depth and rgba (the resolve) with plain stores; the units
@@ -692,16 +693,29 @@ __global__ __launch_bounds__(kScanThreads) void tilescan_kernel(const uint32_t *
 
 // Segment ids grouped by tile: segment i of tile t goes to one of the places
 // [tile_off[t], tile_off[t + 1]) (their order is irrelevant: the tile kernel
-// takes a minimum).  Counts tile_nseg back down to zero.
+// takes a minimum).  Counts tile_nseg back down to zero.  Also empties the
+// key buffer over the tiles of more than one unit, whose units merge into it
+// with atomicMin (the tile kernel writes every other tile's keys whole).
 __global__ __launch_bounds__(kThreads) void segsort_kernel(const uint4 *__restrict__ segs,
                                                            const uint32_t *__restrict__ counters,
                                                            const uint32_t *__restrict__ tile_off,
                                                            uint32_t *__restrict__ tile_nseg,
-                                                           uint32_t *__restrict__ sorted) {
+                                                           uint32_t *__restrict__ sorted,
+                                                           const uint32_t *__restrict__ tile_units, TileGrid tg,
+                                                           uint32_t W, uint32_t H, uint64_t *__restrict__ key) {
   const uint32_t n = counters[kSegTopWord];
   for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
     const uint32_t t = segs[i].x;
     sorted[tile_off[t] + atomicSub(&tile_nseg[t], 1u) - 1u] = i;
+  }
+  for (uint32_t t = blockIdx.x; t < tg.n_tiles; t += gridDim.x) {
+    if (tile_units[t] <= 1) continue;  // (the same for the whole block)
+    const uint32_t tx = t % tg.tiles_x, ty = t / tg.tiles_x;
+    for (int p = threadIdx.x; p < kTilePx; p += kThreads) {
+      const uint32_t gx = (tx << kTileShift) + (p & (kTileSide - 1));
+      const uint32_t gy = (ty << kTileShift) + (p >> kTileShift);
+      if (gx < W && gy < H) key[(size_t)gy * W + gx] = ~0ull;
+    }
   }
 }
 
@@ -976,7 +990,8 @@ hipError_t launch_tiled_splat(const CloudDev &c, const uint2 *chunks, uint32_t *
                                                  (uint32_t)g.unit_cap, counters);
       break;
     case 2:
-      segsort_kernel<<<1024, kThreads, 0, s>>>(b.segs, counters, b.tile_off, b.tile_nseg, b.sorted);
+      segsort_kernel<<<1024, kThreads, 0, s>>>(b.segs, counters, b.tile_off, b.tile_nseg, b.sorted, b.tile_units, tg,
+                                                cam.W, H, key);
       break;
     case 3: {
       const uint64_t grid = std::min<uint64_t>(g.unit_cap, std::max<uint64_t>(2ull * g.n_tiles, 4096));
