@@ -456,35 +456,47 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
   const int gx = tx0 + n;
   const int row0 = wv * R;
   if (head_out) {
+    // per row, the sums run over (mb, j, i) in the same order; the bias and
+    // head weights of a group of 4 channels are read once for all rows
+    float hs[R][3];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int gy = ty0 + row0 + r;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int r = 0; r < R; ++r) hs[r][0] = hs[r][1] = hs[r][2] = 0.f;
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = co0 + mb * 32 + 8 * j + 4 * h;
-          if (c < a.cout) {
-            const float4 b = *reinterpret_cast<const float4 *>(a.bias + c);
-            const float bb[4] = {b.x, b.y, b.z, b.w};
-            float ws[4] = {1.f, 1.f, 1.f, 1.f};
-            if constexpr (MODE == 4 || MODE == 5) {
-              const float4 w4 = *reinterpret_cast<const float4 *>(a.wscale + c);
-              ws[0] = w4.x; ws[1] = w4.y; ws[2] = w4.z; ws[3] = w4.w;
-            }
+      for (int j = 0; j < 4; ++j) {
+        const int c = co0 + mb * 32 + 8 * j + 4 * h;
+        if (c < a.cout) {
+          const float4 b = *reinterpret_cast<const float4 *>(a.bias + c);
+          const float bb[4] = {b.x, b.y, b.z, b.w};
+          float ws[4] = {1.f, 1.f, 1.f, 1.f};
+          if constexpr (MODE == 4 || MODE == 5) {
+            const float4 w4 = *reinterpret_cast<const float4 *>(a.wscale + c);
+            ws[0] = w4.x; ws[1] = w4.y; ws[2] = w4.z; ws[3] = w4.w;
+          }
+          float hw[3][4];  // head weights [output][channel c + i] (rows of cout floats, 16-byte aligned)
+#pragma unroll
+          for (int o = 0; o < 3; ++o) {
+            const float4 w = *reinterpret_cast<const float4 *>(a.head_w + o * a.cout + c);
+            hw[o][0] = w.x; hw[o][1] = w.y; hw[o][2] = w.z; hw[o][3] = w.w;
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float v = fmaxf(scaled<MODE>(acc[mb][r][4 * j + i], ws[i]) + bb[i], 0.f);
-              s0 = fmaf(a.head_w[c + i], v, s0);
-              s1 = fmaf(a.head_w[a.cout + c + i], v, s1);
-              s2 = fmaf(a.head_w[2 * a.cout + c + i], v, s2);
+              hs[r][0] = fmaf(hw[0][i], v, hs[r][0]);
+              hs[r][1] = fmaf(hw[1][i], v, hs[r][1]);
+              hs[r][2] = fmaf(hw[2][i], v, hs[r][2]);
             }
-          }
         }
-      s0 += __shfl_xor(s0, 32, 64);
-      s1 += __shfl_xor(s1, 32, 64);
-      s2 += __shfl_xor(s2, 32, 64);
+      }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int gy = ty0 + row0 + r;
+      const float s0 = hs[r][0] + __shfl_xor(hs[r][0], 32, 64);
+      const float s1 = hs[r][1] + __shfl_xor(hs[r][1], 32, 64);
+      const float s2 = hs[r][2] + __shfl_xor(hs[r][2], 32, 64);
       if (h == 0 && gy < H && gx < W) {
         const size_t HW = (size_t)H * W, p = (size_t)gy * W + gx;
         head_out[p] = s0 + a.head_b[0];
