@@ -708,7 +708,7 @@ static lnr_status ensure_tiled(lnr_context *ctx, Scratch &scr, const TiledSplatG
   const size_t n = std::max<uint32_t>(1, n_points);
   lnr_status st;
   if ((st = ensure(ctx, scr.recs, 8 * n)) != LNR_OK || (st = ensure(ctx, scr.segs, 16 * n)) != LNR_OK ||
-      (st = ensure(ctx, scr.sorted, 4 * n)) != LNR_OK || (st = ensure(ctx, scr.tile_nseg, 4ull * g.n_tiles)) != LNR_OK ||
+      (st = ensure(ctx, scr.sorted, 4 * n)) != LNR_OK || (st = ensure(ctx, scr.tile_nseg, 8ull * g.n_tiles)) != LNR_OK ||
       (st = ensure(ctx, scr.tile_off, 4ull * g.n_tiles + 4)) != LNR_OK ||
       (st = ensure(ctx, scr.tile_units, 4ull * g.n_tiles)) != LNR_OK ||
       (st = ensure(ctx, scr.units, 8ull * g.unit_cap)) != LNR_OK)
@@ -784,7 +784,7 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
   // (the tiled splat writes every key itself: its segment sort empties the
   // keys of the tiles that merge through atomics, so only the counters here)
   LNR_LAUNCH(ctx, "clear", s,
-             launch_clear(out->key, atomic ? npix : 0u, counters, tb.tile_nseg, atomic ? 0u : tg.n_tiles, s));
+             launch_clear(out->key, atomic ? npix : 0u, counters, tb.tile_nseg, atomic ? 0u : 2 * tg.n_tiles, s));
   LNR_LAUNCH(ctx, "cull", s,
              launch_cull(c->d, prm, dev ? &dev->cull : nullptr, static_cast<uint8_t *>(scr.flags.p),
                          static_cast<uint2 *>(scr.chunks.p), counters, s));
@@ -795,8 +795,10 @@ static lnr_status render_impl(lnr_context *ctx, Scratch &scr, const lnr_cloud *c
     if (!soft) LNR_LAUNCH(ctx, "resolve", s, launch_resolve(out->key, c->d.rgbx, out->depth, rgba32, npix, s));
   } else {
     static const char *const names[5] = {"bin", "tilescan", "segsort", "tile", "tileres"};
+    const bool merged = tiled_scan_merged(tg);  // the scan runs inside the segment sort
     for (int stage = 0; stage < 5; ++stage)
-      LNR_LAUNCH(ctx, names[stage], s,
+      if (!(merged && stage == 1))
+        LNR_LAUNCH(ctx, names[stage], s,
                  launch_tiled_splat(c->d, chunks, counters, sc, dev ? &dev->splat : nullptr, (uint32_t)cam->height,
                                     tb, out->key, out->depth, rgba32, stage, s));
   }

@@ -128,6 +128,10 @@ struct TiledSplatGrid {
   uint64_t unit_cap = 0;
 };
 TiledSplatGrid tiled_splat_grid(uint32_t W, uint32_t H, uint32_t n_points);
+// true when the per-tile scan runs inside the segment sort (stage 1 then
+// launches nothing); tile_nseg then holds 2 n_tiles words: the counts, then
+// the fill counters of the sort, both zeroed by launch_clear
+bool tiled_scan_merged(const TiledSplatGrid &g);
 struct TiledSplatBufs {
   uint64_t *recs;
   uint4 *segs;

@@ -473,6 +473,8 @@ __global__ __launch_bounds__(kThreads) void splat_views_kernel(const float *__re
 //             of the tile kernel: up to kSegsPerUnit segments of one tile.
 //   segsort   groups the segment ids by tile, and empties the keys of the
 //             tiles of more than one unit (the only keys not written whole).
+//             Up to kMaxScanTiles tiles, segscan_kernel does both in one
+//             launch (every workgroup repeats the scan in LDS).
 //   tile      one workgroup per unit: LDS z-buffer of the tile over the
 //             unit's records.  A tile of one unit owns its pixels and writes
 //             key, depth and rgba (the resolve) with plain stores; the units
@@ -712,6 +714,80 @@ __global__ __launch_bounds__(kThreads) void segsort_kernel(const uint4 *__restri
     if (tile_units[t] <= 1) continue;  // (the same for the whole block)
     const uint32_t tx = t % tg.tiles_x, ty = t / tg.tiles_x;
     for (int p = threadIdx.x; p < kTilePx; p += kThreads) {
+      const uint32_t gx = (tx << kTileShift) + (p & (kTileSide - 1));
+      const uint32_t gy = (ty << kTileShift) + (p >> kTileShift);
+      if (gx < W && gy < H) key[(size_t)gy * W + gx] = ~0ull;
+    }
+  }
+}
+
+// The scan and the segment sort in one launch, for images of at most
+// kMaxScanTiles tiles: every workgroup takes the exclusive prefix of the
+// per-tile segment counts itself, into LDS (a few thousand words, read from
+// L2; each thread sums a run of consecutive tiles, one block scan of the
+// sums, then each thread walks its run), so no workgroup waits for another; workgroup 0 also writes tile_off,
+// tile_units, units and counters[kUnitsWord] for the tile kernel, as
+// tilescan_kernel does.  The places within a tile come from a second counter
+// array (tile_fill, zeroed with tile_nseg), since tile_nseg is read by every
+// workgroup's scan.  Then, as segsort_kernel: the segment ids grouped by tile,
+// and the keys of the tiles of more than one unit emptied.
+constexpr uint32_t kMaxScanTiles = 8192;
+__global__ __launch_bounds__(kThreads) void segscan_kernel(const uint4 *__restrict__ segs,
+                                                           uint32_t *__restrict__ counters,
+                                                           const uint32_t *__restrict__ tile_nseg,
+                                                           uint32_t *__restrict__ tile_fill,
+                                                           uint32_t *__restrict__ tile_off,
+                                                           uint32_t *__restrict__ tile_units,
+                                                           uint2 *__restrict__ units, uint32_t unit_cap,
+                                                           uint32_t *__restrict__ sorted, TileGrid tg, uint32_t W,
+                                                           uint32_t H, uint64_t *__restrict__ key) {
+  __shared__ uint32_t s_off[kMaxScanTiles + 1];
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  const int tid = threadIdx.x;
+  const bool first = blockIdx.x == 0;
+  // thread tid owns tiles [tid per, (tid + 1) per): its own sums, one block
+  // scan of them, then its tiles' offsets in order
+  const uint32_t per = (tg.n_tiles + kThreads - 1) / kThreads;
+  const uint32_t t_lo = min(tg.n_tiles, tid * per), t_hi = min(tg.n_tiles, t_lo + per);
+  uint32_t my_s = 0, my_u = 0;
+  for (uint32_t t = t_lo; t < t_hi; ++t) {
+    const uint32_t ns = tile_nseg[t];
+    my_s += ns;
+    my_u += max(1u, (ns + kSegsPerUnit - 1) / kSegsPerUnit);
+  }
+  uint32_t tot_s, tot_u;
+  uint32_t seg = block_exclusive_scan<kThreads>(my_s, s_tmp, &tot_s);
+  uint32_t unit = block_exclusive_scan<kThreads>(my_u, s_tmp, &tot_u);
+  for (uint32_t t = t_lo; t < t_hi; ++t) {
+    const uint32_t ns = tile_nseg[t];
+    const uint32_t nu = max(1u, (ns + kSegsPerUnit - 1) / kSegsPerUnit);
+    s_off[t] = seg;
+    if (first) {
+      tile_off[t] = seg;
+      tile_units[t] = nu;
+      for (uint32_t k = 0; k < nu; ++k)
+        if (unit + k < unit_cap) units[unit + k] = make_uint2(t, k * kSegsPerUnit);
+    }
+    seg += ns;
+    unit += nu;
+  }
+  if (tid == 0) {
+    s_off[tg.n_tiles] = tot_s;
+    if (first) {
+      tile_off[tg.n_tiles] = tot_s;
+      counters[kUnitsWord] = min(tot_u, unit_cap);
+    }
+  }
+  __syncthreads();
+  const uint32_t n = counters[kSegTopWord];
+  for (uint32_t i = blockIdx.x * kThreads + tid; i < n; i += gridDim.x * kThreads) {
+    const uint32_t t = segs[i].x;
+    sorted[s_off[t] + atomicAdd(&tile_fill[t], 1u)] = i;
+  }
+  for (uint32_t t = blockIdx.x; t < tg.n_tiles; t += gridDim.x) {
+    if (s_off[t + 1] - s_off[t] <= (uint32_t)kSegsPerUnit) continue;  // one unit (the same for the whole block)
+    const uint32_t tx = t % tg.tiles_x, ty = t / tg.tiles_x;
+    for (int p = tid; p < kTilePx; p += kThreads) {
       const uint32_t gx = (tx << kTileShift) + (p & (kTileSide - 1));
       const uint32_t gy = (ty << kTileShift) + (p >> kTileShift);
       if (gx < W && gy < H) key[(size_t)gy * W + gx] = ~0ull;
@@ -959,6 +1035,8 @@ hipError_t launch_clear(uint64_t *key, uint32_t npix, uint32_t *counters, uint32
   return hipGetLastError();
 }
 
+bool tiled_scan_merged(const TiledSplatGrid &g) { return g.n_tiles <= kMaxScanTiles; }
+
 TiledSplatGrid tiled_splat_grid(uint32_t W, uint32_t H, uint32_t n_points) {
   TiledSplatGrid g;
   g.tiles_x = (W + kTileSide - 1) >> kTileShift;
@@ -986,12 +1064,18 @@ hipError_t launch_tiled_splat(const CloudDev &c, const uint2 *chunks, uint32_t *
                                                            nullptr, tg, b.recs, b.segs, b.tile_nseg);
       break;
     case 1:
+      if (tiled_scan_merged(g)) return hipSuccess;  // taken by the segment sort
       tilescan_kernel<<<1, kScanThreads, 0, s>>>(b.tile_nseg, tg, b.tile_off, b.tile_units, b.units,
                                                  (uint32_t)g.unit_cap, counters);
       break;
     case 2:
-      segsort_kernel<<<1024, kThreads, 0, s>>>(b.segs, counters, b.tile_off, b.tile_nseg, b.sorted, b.tile_units, tg,
-                                                cam.W, H, key);
+      if (tiled_scan_merged(g))
+        segscan_kernel<<<256, kThreads, 0, s>>>(b.segs, counters, b.tile_nseg, b.tile_nseg + g.n_tiles, b.tile_off,
+                                                b.tile_units, b.units, (uint32_t)g.unit_cap, b.sorted, tg, cam.W, H,
+                                                key);
+      else
+        segsort_kernel<<<1024, kThreads, 0, s>>>(b.segs, counters, b.tile_off, b.tile_nseg, b.sorted, b.tile_units,
+                                                  tg, cam.W, H, key);
       break;
     case 3: {
       const uint64_t grid = std::min<uint64_t>(g.unit_cap, std::max<uint64_t>(2ull * g.n_tiles, 4096));
