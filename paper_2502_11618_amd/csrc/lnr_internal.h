@@ -117,11 +117,13 @@ hipError_t launch_chunk_count(const uint32_t *cell_start, uint32_t n_cells, uint
 // splat's per-tile segment counts (n_tiles words)
 hipError_t launch_clear(uint64_t *key, uint32_t npix, uint32_t *counters, uint32_t *tile_nseg, uint32_t n_tiles,
                         hipStream_t s);
-// Screen-tiled splat (32 x 32 pixel tiles), in five launches (stage 0..4:
-// bin, tilescan, segsort, tile, tileres).  Scratch per render for a cloud of
-// n points: recs u64[n] (a work item's records at its points' positions),
-// segs uint4[n] and sorted u32[n] (at most one segment per record),
-// tile_nseg, tile_units u32[n_tiles], tile_off u32[n_tiles + 1], units
+// Screen-tiled splat (32 x 32 pixel tiles), in up to five launches (stage
+// 0..4: bin, tilescan, segsort, tile, tileres; stage 1 launches nothing when
+// tiled_scan_merged(), the segment sort then taking the scan).  Scratch per
+// render for a cloud of n points: recs u64[n] (a work item's records at its
+// points' positions), segs uint4[n] and sorted u32[n] (at most one segment
+// per record), tile_nseg u32[2 n_tiles] (the counts, then the merged sort's
+// fill counters), tile_units u32[n_tiles], tile_off u32[n_tiles + 1], units
 // uint2[unit_cap].
 struct TiledSplatGrid {
   uint32_t tiles_x = 0, tiles_y = 0, n_tiles = 0;
